@@ -1,0 +1,574 @@
+"""Pins of the CPU oracle against facts fixed by the paper and the mathematics.
+
+Nothing here compares the oracle with itself: every check is a closed form,
+an invariant, an exact solution, a brute-force order measurement or an
+independent implementation (the torch reference, written separately with
+whole-array operations).
+"""
+import math
+import os
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import workloads as W
+from oracle import exact_riemann as er
+from oracle import torch_ref as TR
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+ULP = np.finfo(np.float64).eps
+
+
+def _golden(name):
+    out = {}
+    with open(os.path.join(GOLDEN, name)) as f:
+        for line in f:
+            line = line.strip()
+            if line and not line.startswith("#"):
+                k, v = line.split()
+                out[k] = float(v)
+    return out
+
+
+def _case_1d_two_fluid(n, u0=100.0, p0=1e5, bc=W.PERIODIC):
+    dx = 1.0 / n
+    x = (np.arange(n) + 0.5) * dx
+    aa = W._tanh_fraction(np.abs(x - 0.5) - 0.2, dx)
+    w = W._two_fluid_w(1 - aa, 1000.0, 1.0, [np.full(n, u0)], np.full(n, p0)).reshape(6, 1, 1, n)
+    return W.Case("interface", 1, (n, 1, 1), 2, (dx, 1.0, 1.0), (6.12, 1.4), (3.43e8, 0.0),
+                  (bc,) * 3, (bc,) * 3, w)
+
+
+# --------------------------------------------------------------------------
+# C-1 / C-3: closure
+# --------------------------------------------------------------------------
+def test_cons_prim_cons_roundtrip():
+    """q -> w -> q returns every conservative field to within 4 ulp."""
+    c = W.random_case(2, (40, 36), nf=2, seed=11, speed=300.0)
+    O = oracle.Oracle(c)
+    q = O.prim_to_cons(c.w)
+    q2 = O.prim_to_cons(O.cons_to_prim(q))
+    err = np.abs(q2 - q) / np.maximum(np.abs(q), np.finfo(float).tiny)
+    assert err.max() <= 4 * ULP, err.max()
+
+
+def test_pure_fluid_sound_speed_closed_form():
+    """alpha = (1, 0): the mixture c^2 is gamma_1 (p + pi_1) / rho_1 (Sec. 2.1.1)."""
+    n = 64
+    rng = np.random.default_rng(5)
+    rho = rng.uniform(800, 1200, n)
+    p = rng.uniform(1e4, 1e9, n)
+    u = rng.uniform(-100, 100, n)
+    w = np.stack([rho, np.zeros(n), u, p, np.ones(n), np.zeros(n)]).reshape(6, 1, 1, n)
+    c = W.Case("pure", 1, (n, 1, 1), 2, (0.1, 1, 1), (6.12, 1.4), (3.43e8, 0.0), (1,) * 3, (1,) * 3, w)
+    O = oracle.Oracle(c)
+    c2 = O.sound_speed_sq(O.prim_to_cons(w))[0, 0]
+    exact = 6.12 * (p + 3.43e8) / rho
+    # p is recovered from rho E = Gamma p + Pi + ke with relative error ~ ulp * (Pi + ke)/(Gamma p)
+    assert np.allclose(c2, exact, rtol=64 * ULP, atol=0)
+
+
+def test_identical_fluids_reduce_to_single_fluid():
+    """Two copies of one gas in equal parts reproduce the single-gas RHS bit for bit.
+
+    With alpha = 1/2 everywhere, every partial density is half the density
+    (an exact scaling) and, once eps is negligible against beta, WENO commutes
+    with that scaling; Gamma and Pi equal the single-gas values exactly.
+    """
+    c1 = W.random_case(2, (24, 20), nf=1, seed=4, speed=500.0)
+    c1.weno_eps = 1e-40
+    O1 = oracle.Oracle(c1)
+    q1 = O1.prim_to_cons(c1.w)
+    rho = c1.w[0]
+    half = np.full_like(rho, 0.5)
+    w2 = np.stack([0.5 * rho, 0.5 * rho, c1.w[1], c1.w[2], c1.w[3], half, half])
+    c2 = W.Case("ident", 2, c1.n, 2, c1.dx, (1.4, 1.4), (0.0, 0.0), c1.bc_lo, c1.bc_hi, w2,
+                weno_eps=1e-40)
+    O2 = oracle.Oracle(c2)
+    q2 = O2.prim_to_cons(w2)
+    r1, r2 = O1.rhs(q1), O2.rhs(q2)
+    assert np.array_equal(r2[0], 0.5 * r1[0]) and np.array_equal(r2[1], 0.5 * r1[0])
+    for a, b in [(r1[1], r2[2]), (r1[2], r2[3]), (r1[3], r2[4])]:
+        assert np.array_equal(a, b)
+    assert np.all(r2[5] == 0.0) and np.all(r2[6] == 0.0)
+
+
+# --------------------------------------------------------------------------
+# C-4: WENO5-JS
+# --------------------------------------------------------------------------
+def _avg_poly(coef, a, b):
+    """Exact cell average of sum_k coef[k] x^k over [a, b]."""
+    tot = 0.0
+    for k, ck in enumerate(coef):
+        tot += ck * (b ** (k + 1) - a ** (k + 1)) / (k + 1)
+    return tot / (b - a)
+
+
+def test_weno_constants_exact():
+    for v in [0.375, -12.5, 1024.0, 3.0]:
+        f = np.full(5, v)
+        assert oracle.weno5_js_left(f) == v
+        assert oracle.weno5_js_right(f) == v
+
+
+@pytest.mark.parametrize("seed", range(5))
+def test_weno_reproduces_quadratics(seed):
+    """Every candidate is exact for quadratics, so any convex combination is."""
+    rng = np.random.default_rng(seed)
+    coef = rng.normal(size=3)
+    h = 0.1
+    f = np.array([_avg_poly(coef, (k - 2.5) * h, (k - 1.5) * h) for k in range(5)])
+    xr = 0.5 * h  # right face of the centre cell [-h/2, h/2]
+    exact_r = sum(ck * xr ** k for k, ck in enumerate(coef))
+    exact_l = sum(ck * (-xr) ** k for k, ck in enumerate(coef))
+    assert abs(oracle.weno5_js_left(f) - exact_r) <= 1e-13 * (1 + abs(exact_r))
+    assert abs(oracle.weno5_js_right(f) - exact_l) <= 1e-13 * (1 + abs(exact_l))
+
+
+@pytest.mark.parametrize("seed", range(5))
+def test_weno_linear_limit_is_fifth_order_upwind(seed):
+    """eps >> beta gives the linear weights: the (2,-13,47,27,-3)/60 scheme, exact for quartics."""
+    rng = np.random.default_rng(seed)
+    coef = rng.normal(size=5)
+    h = 0.05
+    f = np.array([_avg_poly(coef, (k - 2.5) * h, (k - 1.5) * h) for k in range(5)])
+    lin = (2 * f[0] - 13 * f[1] + 47 * f[2] + 27 * f[3] - 3 * f[4]) / 60.0
+    exact = sum(ck * (0.5 * h) ** k for k, ck in enumerate(coef))
+    got = oracle.weno5_js_left(f, eps=1e30)
+    assert abs(got - lin) <= 1e-13 * (1 + abs(lin))
+    assert abs(got - exact) <= 1e-12 * (1 + abs(exact))
+
+
+def test_weno_complement_symmetry():
+    """beta is invariant under f -> 1 - f and candidate weights sum to one."""
+    rng = np.random.default_rng(7)
+    for _ in range(200):
+        f = rng.uniform(0, 1, 5)
+        f[rng.integers(0, 5)] = rng.choice([0.0, 1.0])
+        a = oracle.weno5_js_left(f)
+        b = oracle.weno5_js_left(1.0 - f)
+        assert abs((1.0 - b) - a) <= 8 * ULP
+
+
+def test_weno_nonoscillatory_at_step():
+    """A step gives a value inside the data range (essentially non-oscillatory)."""
+    f = np.array([0.0, 0.0, 0.0, 1.0, 1.0])
+    v = oracle.weno5_js_left(f)
+    assert 0.0 <= v < 1e-6 * 50
+    f = np.array([0.0, 0.0, 1.0, 1.0, 1.0])
+    v = oracle.weno5_js_left(f)
+    assert abs(v - 1.0) < 1e-6 * 50
+
+
+# --------------------------------------------------------------------------
+# C-5: HLLC
+# --------------------------------------------------------------------------
+def _prim_state(rng, nf=2, D=3, speed=100.0):
+    if nf == 2:
+        a = rng.uniform(1e-6, 1 - 1e-6)
+        return np.array([a * rng.uniform(900, 1100), (1 - a) * rng.uniform(0.5, 2)]
+                        + list(rng.uniform(-speed, speed, D)) + [rng.uniform(1e4, 1e7), a, 1 - a])
+    return np.array([rng.uniform(0.5, 2)] + list(rng.uniform(-speed, speed, D)) + [rng.uniform(0.5, 2)])
+
+
+def _oracle_for(D, nf=2):
+    if nf == 2:
+        return oracle.Oracle(ndim=D, n=(4,) * D, num_fluids=2, dx=(0.1,) * D, gamma=(6.12, 1.4),
+                             pi_inf=(3.43e8, 0.0), bc_lo=(1,) * 3, bc_hi=(1,) * 3)
+    return oracle.Oracle(ndim=D, n=(4,) * D, num_fluids=1, dx=(0.1,) * D, gamma=(1.4, 1.4),
+                         pi_inf=(0.0, 0.0), bc_lo=(1,) * 3, bc_hi=(1,) * 3)
+
+
+def _physical_flux(O, d, w, nf, D):
+    G = [1 / (g - 1) for g in O.P.gamma]
+    Pc = [g * p / (g - 1) for g, p in zip(O.P.gamma, O.P.pi_inf)]
+    rho = w[:nf].sum()
+    u = w[nf:nf + D]
+    p = w[nf + D]
+    if nf == 2:
+        Gam = w[nf + D + 1] * G[0] + w[nf + D + 2] * G[1]
+        Pi = w[nf + D + 1] * Pc[0] + w[nf + D + 2] * Pc[1]
+    else:
+        Gam, Pi = G[0], Pc[0]
+    E = Gam * p + Pi + 0.5 * rho * (u @ u)
+    F = list(w[:nf] * u[d]) + [rho * u[e] * u[d] + (p if e == d else 0) for e in range(D)] + [(E + p) * u[d]]
+    if nf == 2:
+        F += list(w[nf + D + 1:] * u[d])
+    return np.array(F)
+
+
+@pytest.mark.parametrize("nf,D", [(2, 3), (2, 2), (1, 3), (1, 1)])
+def test_hllc_consistency(nf, D):
+    """F(w, w) equals the physical flux."""
+    O = _oracle_for(D, nf)
+    rng = np.random.default_rng(1)
+    for _ in range(50):
+        w = _prim_state(rng, nf, D)
+        d = int(rng.integers(0, D))
+        F, uf, rc = O.hllc(d, w, w)
+        assert rc == 0
+        Fp = _physical_flux(O, d, w, nf, D)
+        scale = np.abs(Fp) + abs(w[nf + D]) + 1e-300
+        assert np.all(np.abs(F - Fp) <= 1e-12 * scale)
+        assert abs(uf - w[nf + d]) <= 1e-12 * (abs(w[nf + d]) + 1)
+
+
+def test_hllc_supersonic_upwind_exact():
+    """S_L >= 0 gives the left physical flux exactly; S_R <= 0 the right one."""
+    O = _oracle_for(1, 1)
+    wl = np.array([1.0, 3.0, 1.0])    # c ~ 1.18, u = 3: supersonic to the right
+    wr = np.array([0.5, 2.5, 0.8])
+    F, uf, rc = O.hllc(0, wl, wr)
+    assert np.array_equal(F, _physical_flux(O, 0, wl, 1, 1)) and uf == 3.0
+    wl2, wr2 = np.array([0.5, -2.5, 0.8]), np.array([1.0, -3.0, 1.0])
+    F, uf, rc = O.hllc(0, wl2, wr2)
+    assert np.array_equal(F, _physical_flux(O, 0, wr2, 1, 1)) and uf == -3.0
+
+
+def test_hllc_contact_upwinding():
+    """Equal u and p on both sides: the flux is the upwind physical flux (a resolved contact)."""
+    O = _oracle_for(2, 2)
+    rng = np.random.default_rng(2)
+    for sgn in (1.0, -1.0):
+        u, v, p = sgn * 37.0, 11.0, 2.5e5
+        aL, aR = 0.9, 1e-6
+        wl = np.array([aL * 1000, (1 - aL) * 1.0, u, v, p, aL, 1 - aL])
+        wr = np.array([aR * 1010, (1 - aR) * 1.2, u, v, p, aR, 1 - aR])
+        F, uf, rc = O.hllc(0, wl, wr)
+        up = wl if sgn > 0 else wr
+        Fp = _physical_flux(O, 0, up, 2, 2)
+        assert np.all(np.abs(F - Fp) <= 1e-9 * (np.abs(Fp) + p))
+        assert abs(uf - u) <= 1e-12 * abs(u)
+
+
+def test_hllc_mirror_states_zero_contact_speed():
+    """A state against its mirror image (slip wall) gives S* = 0: no mass or volume flux."""
+    O = _oracle_for(2, 2)
+    rng = np.random.default_rng(4)
+    for _ in range(50):
+        w = _prim_state(rng, 2, 2, speed=300)
+        m = w.copy()
+        m[2] = -m[2]
+        F, uf, rc = O.hllc(0, w, m)
+        assert uf == 0.0
+        assert F[5] == 0.0 and F[6] == 0.0
+        assert abs(F[0]) <= 1e-12 * abs(w[0] * w[2]) + 1e-300
+        # the normal momentum flux is the star pressure p + rho (S_L - u)(S* - u) with S* = 0
+        rho = w[0] + w[1]
+        Gam = w[5] / 5.12 + w[6] / 0.4
+        Pi = w[5] * 6.12 * 3.43e8 / 5.12
+        c = math.sqrt(((Gam + 1) * w[4] + Pi) / (Gam * rho))
+        SL = min(w[2] - c, -w[2] - c)
+        pstar = w[4] + rho * (SL - w[2]) * (0.0 - w[2])
+        assert abs(F[2] - pstar) <= 1e-9 * (abs(pstar) + w[4])
+
+
+def test_hllc_flags_nonphysical_state():
+    O = _oracle_for(1, 1)
+    F, uf, rc = O.hllc(0, np.array([1.0, 0.0, -1.0]), np.array([1.0, 0.0, 1.0]))
+    assert rc == 1
+
+
+# --------------------------------------------------------------------------
+# C-2 / C-6: RHS assembly, ghost layers, invariances
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("bc", [W.PERIODIC, W.EXTRAP, W.SLIPWALL])
+def test_uniform_state_zero_rhs(bc):
+    n = (10, 9, 8)
+    w = np.zeros((8,) + n[::-1])
+    w[0], w[1], w[2], w[3], w[4], w[5], w[6], w[7] = 300.0, 0.7, 0.0, 0.0, 0.0, 2e5, 0.3, 0.7
+    if bc != W.SLIPWALL:
+        w[2], w[3], w[4] = 12.0, -5.0, 3.0
+    c = W.Case("u", 3, n, 2, (0.1, 0.1, 0.1), (6.12, 1.4), (3.43e8, 0.0), (bc,) * 3, (bc,) * 3, w)
+    O = oracle.Oracle(c)
+    r = O.rhs(O.prim_to_cons(w))
+    assert np.all(r == 0.0)
+
+
+def test_periodic_telescoping_conservation():
+    c = W.random_case(2, (32, 28), nf=2, seed=8, bc=(W.PERIODIC, W.PERIODIC))
+    O = oracle.Oracle(c)
+    r = O.rhs(O.prim_to_cons(c.w))
+    for v in range(5):  # partial densities, momenta, energy
+        assert abs(r[v].sum()) <= 1e-13 * np.abs(r[v]).sum()
+
+
+def test_transpose_xy_bitwise():
+    c = W.random_case(2, (20, 20), nf=2, seed=9, bc=(W.SLIPWALL, W.EXTRAP))
+    O = oracle.Oracle(c)
+    q = O.prim_to_cons(c.w)
+    r = O.rhs(q)
+    qt = q.transpose(0, 1, 3, 2)[[0, 1, 3, 2, 4, 5, 6]].copy()
+    ct = W.Case("t", 2, (20, 20, 1), 2, c.dx, c.gamma, c.pi_inf, (W.EXTRAP, W.SLIPWALL, 1),
+                (W.EXTRAP, W.SLIPWALL, 1), qt)
+    rt = oracle.Oracle(ct).rhs(qt)
+    assert np.array_equal(rt, r.transpose(0, 1, 3, 2)[[0, 1, 3, 2, 4, 5, 6]])
+
+
+def test_one_d_embedding_bitwise():
+    c1 = W.random_case(1, (40,), nf=2, seed=10)
+    O1 = oracle.Oracle(c1)
+    q1 = O1.prim_to_cons(c1.w)
+    r1 = O1.rhs(q1)
+    w2 = np.zeros((7, 1, 5, 40))
+    for v, v2 in zip(range(6), [0, 1, 2, 4, 5, 6]):
+        w2[v2] = c1.w[v]
+    c2 = W.Case("e", 2, (40, 5, 1), 2, (c1.dx[0], 0.3, 1), c1.gamma, c1.pi_inf, (1, 0, 1), (1, 0, 1), w2)
+    O2 = oracle.Oracle(c2)
+    r2 = O2.rhs(O2.prim_to_cons(w2))
+    for v, v2 in zip(range(6), [0, 1, 2, 4, 5, 6]):
+        assert np.array_equal(r2[v2], np.broadcast_to(r1[v], r2[v2].shape))
+    assert np.all(r2[3] == 0.0)
+
+
+def test_periodic_shift_bitwise():
+    c = W.random_case(2, (24, 16), nf=2, seed=12, bc=(W.PERIODIC, W.PERIODIC))
+    O = oracle.Oracle(c)
+    q = O.prim_to_cons(c.w)
+    r = O.rhs(q)
+    qs = np.roll(q, (5, -3), axis=(3, 2)).copy()
+    assert np.array_equal(O.rhs(qs), np.roll(r, (5, -3), axis=(3, 2)))
+
+
+def test_slip_wall_equals_mirror_doubled_domain():
+    c = W.random_case(2, (16, 12), nf=2, seed=13, bc=(W.EXTRAP, W.EXTRAP))
+    c.bc_hi = (W.SLIPWALL, W.EXTRAP, W.EXTRAP)
+    O = oracle.Oracle(c)
+    q = O.prim_to_cons(c.w)
+    r = O.rhs(q)
+    mirror = q[:, :, :, ::-1].copy()
+    mirror[2] = -mirror[2]
+    qd = np.ascontiguousarray(np.concatenate([q, mirror], axis=3))
+    cd = W.Case("d", 2, (32, 12, 1), 2, c.dx, c.gamma, c.pi_inf, (1, 1, 1), (1, 1, 1), qd)
+    rd = oracle.Oracle(cd).rhs(qd)
+    assert np.array_equal(rd[:, :, :, :16], r)
+
+
+def test_rhs_cells_matches_full_rhs_bitwise():
+    c = W.random_case(3, (14, 12, 10), nf=2, seed=14, bc=(W.SLIPWALL, W.PERIODIC, W.EXTRAP))
+    O = oracle.Oracle(c)
+    q = O.prim_to_cons(c.w)
+    r = O.rhs(q)
+    cells = np.random.default_rng(0).choice(c.ncell, size=300, replace=False)
+    got = O.rhs_cells(q, cells)
+    assert np.array_equal(got, r.reshape(c.neq, -1)[:, cells].T)
+
+
+@pytest.mark.parametrize("nd,n,nf,bc", [(1, (40,), 1, (1,)), (2, (24, 20), 2, (2, 1)),
+                                         (3, (12, 10, 9), 2, (1, 2, 0)), (1, (30,), 2, (2,))])
+def test_independent_torch_implementation_agrees_bitwise(nd, n, nf, bc):
+    """The whole-array torch version (independent code) reproduces the oracle bit for bit."""
+    c = W.random_case(nd, n, nf=nf, seed=3, bc=bc)
+    O = oracle.Oracle(c)
+    q = O.prim_to_cons(c.w)
+    P = TR.Problem.from_case(c)
+    qt = torch.from_numpy(q)
+    assert np.array_equal(O.rhs(q), TR.rhs(P, qt).numpy())
+    assert np.array_equal(q, TR.prim_to_cons(P, torch.from_numpy(c.w)).numpy())
+    dt = 0.3 / O.max_signal(q)
+    q2 = q.copy()
+    O.step(q2, dt_fixed=dt)
+    assert np.array_equal(q2, TR.step(P, qt, dt).numpy())
+
+
+def test_nonfinite_state_is_flagged():
+    c = W.random_case(1, (20,), nf=1, seed=1)
+    O = oracle.Oracle(c)
+    q = O.prim_to_cons(c.w)
+    q[2, 0, 0, 7] = -1e6  # energy below kinetic: negative pressure
+    with pytest.raises(oracle.OracleError) as e:
+        O.rhs(q)
+    assert e.value.code == oracle.ORC_ERR_NONFINITE
+
+
+# --------------------------------------------------------------------------
+# C-6 equilibrium, C-7 / C-8 time stepping
+# --------------------------------------------------------------------------
+def test_pressure_velocity_equilibrium_across_interface():
+    """An advected air-water interface keeps p and u uniform (Allaire model)."""
+    c = _case_1d_two_fluid(100)
+    O = oracle.Oracle(c)
+    q = O.prim_to_cons(c.w)
+    O.run(q, 400, cfl=0.5)
+    w = O.cons_to_prim(q)
+    assert np.abs(w[3] / 1e5 - 1).max() <= 1e-10
+    assert np.abs(w[2] / 100.0 - 1).max() <= 1e-10
+
+
+def test_periodic_conservation_over_steps():
+    c = W.random_case(2, (24, 24), nf=2, seed=15, bc=(W.PERIODIC, W.PERIODIC), speed=150.0)
+    O = oracle.Oracle(c)
+    q = O.prim_to_cons(c.w)
+    s0 = O.conserved_sums(q)
+    a0 = np.abs(q).sum(axis=(1, 2, 3)) * c.dx[0] * c.dx[1]
+    O.run(q, 30, cfl=0.5)
+    s1 = O.conserved_sums(q)
+    for v in range(5):
+        assert abs(s1[v] - s0[v]) <= 1e-13 * a0[v] * 30
+
+
+def test_cfl_closed_form_uniform():
+    n = 8
+    w = np.zeros((8, n, n, n))
+    w[0], w[1], w[5], w[6], w[7] = 0.6 * 1000, 0.4 * 1.0, 1e5, 0.6, 0.4
+    w[2], w[3], w[4] = 10.0, -20.0, 30.0
+    dx = (0.1, 0.2, 0.05)
+    c = W.Case("cfl", 3, (n, n, n), 2, dx, (6.12, 1.4), (3.43e8, 0.0), (0,) * 3, (0,) * 3, w)
+    O = oracle.Oracle(c)
+    q = O.prim_to_cons(w)
+    s = O.max_signal(q)
+    Gam = 0.6 / 5.12 + 0.4 / 0.4
+    Pi = 0.6 * 6.12 * 3.43e8 / 5.12
+    cs = math.sqrt(((Gam + 1) * 1e5 + Pi) / (Gam * 600.4))
+    exact = (10 + cs) / 0.1 + (20 + cs) / 0.2 + (30 + cs) / 0.05
+    assert abs(s - exact) <= 1e-9 * exact
+    q2 = q.copy()
+    assert O.step(q2, cfl=0.5) == pytest.approx(0.5 / s, rel=1e-15)
+    assert np.allclose(q2, q, rtol=1e-12, atol=0)
+
+
+def test_rk3_temporal_order():
+    """Shu-Osher SSP-RK3 is third order in time (Richardson with dt, dt/2, dt/4)."""
+    c = W.advection_1d(32, amplitude=0.25, gamma2=1.6)
+    O = oracle.Oracle(c)
+    q0 = O.prim_to_cons(c.w)
+    T = 0.25
+    sols = []
+    for k in (20, 40, 80):
+        q = q0.copy()
+        O.run(q, k, dt_fixed=T / k)
+        sols.append(q[4].ravel())
+    ratio = np.linalg.norm(sols[0] - sols[1]) / np.linalg.norm(sols[1] - sols[2])
+    assert 7.0 < ratio < 9.0, ratio  # 2^3
+
+
+@pytest.mark.parametrize("amp,g2", [(1.0, 1.4), (0.25, 1.6)])
+def test_fifth_order_advection_convergence(amp, g2):
+    """The paper's 1D two-component advection problem (Sec. 3.5): RMS error after
+    five periods converges at fifth order (dt ~ h^(5/3) keeps the RK3 error below)."""
+    errs = []
+    Ns = [16, 32, 64]
+    for N in Ns:
+        c = W.advection_1d(N, amplitude=amp, gamma2=g2)
+        O = oracle.Oracle(c)
+        q = O.prim_to_cons(c.w)
+        T = 5.0
+        h = 1.0 / N
+        ns = int(np.ceil(T / (0.25 * h ** (5.0 / 3.0))))
+        O.run(q, ns, dt_fixed=T / ns)
+        ex = W.advection_exact_average(N, amp, T)
+        errs.append(np.sqrt(np.mean((q[4, 0, 0] - ex) ** 2)))
+    orders = np.log2(np.array(errs[:-1]) / np.array(errs[1:]))
+    assert orders[-1] >= 4.5, orders
+
+
+# --------------------------------------------------------------------------
+# Sod (C0) against the exact Riemann solution
+# --------------------------------------------------------------------------
+def _sod_errors(N):
+    c = W.sod(N)
+    O = oracle.Oracle(c)
+    q = O.prim_to_cons(c.w)
+    O.run_to(q, 0.2, 0.5)
+    w = O.cons_to_prim(q)[:, 0, 0]
+    x = (np.arange(N) + 0.5) / N
+    r, u, p = er.sample((1, 0, 1), (0.125, 0, 0.1), (x - 0.5) / 0.2)
+    return x, w, (r, u, p)
+
+
+def test_sod_against_exact_solution():
+    x, w, (r, u, p) = _sod_errors(200)
+    assert np.mean(np.abs(w[0] - r)) <= 4e-3
+    assert w[0].max() <= 1.0 * 1.02 and w[0].min() >= 0.125 * 0.98
+    star = _golden("toro_test1_star.txt")
+    ps, us = star["p_star"], star["u_star"]
+    plateau = (x > 0.52) & (x < 0.66)
+    assert abs(w[2][plateau].mean() / ps - 1) <= 5e-3
+    assert abs(w[1][plateau].mean() / us - 1) <= 5e-3
+    assert abs(w[0][plateau].mean() / star["rho_star_left"] - 1) <= 5e-3
+    right = (x > 0.72) & (x < 0.83)
+    assert abs(w[0][right].mean() / star["rho_star_right"] - 1) <= 5e-3
+
+
+def test_sod_l1_convergence():
+    errs = []
+    for N in (100, 200, 400):
+        x, w, (r, u, p) = _sod_errors(N)
+        errs.append(np.mean(np.abs(w[0] - r)))
+    rates = np.log2(np.array(errs[:-1]) / np.array(errs[1:]))
+    assert np.all(rates >= 0.6), rates
+
+
+# --------------------------------------------------------------------------
+# Exact Riemann solver pins
+# --------------------------------------------------------------------------
+def test_exact_solver_matches_textbook_table():
+    star = _golden("toro_test1_star.txt")
+    ps, us = er.star_state((1, 0, 1), (0.125, 0, 0.1))
+    assert round(ps, 5) == star["p_star"] and round(us, 5) == star["u_star"]
+    xi = np.array([0.5, 1.2])
+    r, u, p = er.sample((1, 0, 1), (0.125, 0, 0.1), xi)
+    assert round(r[0], 5) == star["rho_star_left"] and round(r[1], 5) == star["rho_star_right"]
+
+
+def test_exact_solver_jump_conditions():
+    """Rankine-Hugoniot across the shock, isentrope and Riemann invariant across the fan."""
+    g = 1.4
+    L, R = (1.0, 0.0, 1.0), (0.125, 0.0, 0.1)
+    ws = er.wave_speeds(L, R)
+    s = ws["shock"]
+    r, u, p = er.sample(L, R, np.array([s - 1e-9, s + 1e-9, -1.0, 0.3 * ws["head"] + 0.7 * ws["tail"]]))
+    # shock frame mass and momentum flux continuity
+    m1, m2 = r[0] * (u[0] - s), r[1] * (u[1] - s)
+    assert abs(m1 - m2) <= 1e-9
+    assert abs((r[0] * (u[0] - s) ** 2 + p[0]) - (r[1] * (u[1] - s) ** 2 + p[1])) <= 1e-9
+    e = lambda rr, uu, pp: pp / ((g - 1) * rr) + 0.5 * (uu - s) ** 2 + pp / rr
+    assert abs(e(r[0], u[0], p[0]) - e(r[1], u[1], p[1])) <= 1e-9
+    # inside the rarefaction: p/rho^g and u + 2c/(g-1) equal their left values
+    c = lambda rr, pp: math.sqrt(g * pp / rr)
+    assert abs(p[3] / r[3] ** g - p[2] / r[2] ** g) <= 1e-12
+    assert abs((u[3] + 2 * c(r[3], p[3]) / (g - 1)) - (u[2] + 2 * c(r[2], p[2]) / (g - 1))) <= 1e-12
+
+
+def test_water_shock_is_single_right_running_wave():
+    """The shock-cylinder post-shock state (stiffened-gas Rankine-Hugoniot) against the exact solver."""
+    rho1, u1, p1, s = W.water_shock_state(1.5)
+    ps, us = er.star_state((rho1, u1, p1), (1000.0, 0.0, 1e5), gamma=6.12, pi_inf=3.43e8)
+    assert abs(ps - p1) <= 1e-9 * p1 and abs(us - u1) <= 1e-9 * u1
+    ws = er.wave_speeds((rho1, u1, p1), (1000.0, 0.0, 1e5), gamma=6.12, pi_inf=3.43e8)
+    assert abs(ws["shock"] - s) <= 1e-9 * s
+
+
+# --------------------------------------------------------------------------
+# Reference gradients (torch autograd through the same discretization)
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("nd,n,bc,interface,jump", [
+    (1, (24,), (W.SLIPWALL,), False, 1.0),
+    (2, (12, 10), (W.EXTRAP, W.PERIODIC), False, 1.0),
+    (2, (12, 10), (W.EXTRAP, W.PERIODIC), True, 3.0)])
+def test_reference_rhs_gradient_matches_finite_differences(nd, n, bc, interface, jump):
+    """<v, J^T lam> from autograd equals <(L(q+hv) - L(q-hv))/2h, lam> from the C oracle.
+
+    Directions v are smooth fields scaled by |q| (white-noise directions change
+    the WENO smoothness indicators so much that the central difference leaves
+    its asymptotic range); Richardson extrapolation over h = 4e-9, 2e-9; a wrong term shows as an O(1e-3..1) error.
+    """
+    c = W.random_case(nd, n, nf=2, seed=21, bc=bc, speed=50.0, pressure_jump=jump, interface=interface)
+    O = oracle.Oracle(c)
+    q = O.prim_to_cons(c.w)
+    P = TR.Problem.from_case(c)
+    rng = np.random.default_rng(0)
+    for _ in range(2):
+        v = np.stack([W._smooth_field(rng, q.shape[1:], nd) for _ in range(q.shape[0])]) * np.abs(q)
+        lam = rng.normal(size=q.shape)
+        qt = torch.from_numpy(q.copy()).requires_grad_(True)
+        (g,) = torch.autograd.grad(TR.rhs(P, qt), qt, torch.from_numpy(lam))
+        lhs = float((g.numpy() * v).sum())
+        est = []
+        for h in (4e-9, 2e-9):
+            fd = (O.rhs(q + h * v) - O.rhs(q - h * v)) / (2 * h)
+            est.append(float((fd * lam).sum()))
+        rich = (4 * est[1] - est[0]) / 3
+        assert abs(rich / lhs - 1) <= 1e-5, (lhs, est)
