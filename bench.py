@@ -1,0 +1,187 @@
+#!/usr/bin/env python3
+"""Grind-time benchmark of the five-equation RHS step on one MI355X.
+
+Workload: the 3D air-water bubble cloud, 256^3 cells, two fluids (8 rows),
+WENO5-JS + HLLC + SSP-RK3 at CFL 0.5, seeded synthetic initial condition.
+One "step" is one SSP-RK3 step: a signal-speed reduction for dt and three RHS
+evaluations (three axis passes each, the last fused with the stage update),
+with the state resident in HBM.
+
+Printed (one JSON line on stdout): FP64 grind time in ns per cell per RK stage
+(`value`), the FP32 form's grind time, speedup and per-field error against the
+FP64 path, the roofline of the dominant kernel (HIP events around every launch
+on its own stream during the timed region), and the CPU oracle timed on this
+host's cores on a bounded sample of the same workload.
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "grind time ns/cell/RK-stage FP64 vs FP32 + %HBM peak; adjoint/forward cost"
+HBM_PEAK_GBS = 8000.0
+FP64_PEAK_TFLOPS = 78.6
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def pass_bytes_per_cell(kind, neq, esize, ndim, stage_mix=(1, 1, 1)):
+    """Algorithmic HBM bytes per cell of one launch of a pass kind.
+
+    x pass writes the RHS accumulator (read q, write acc); middle passes read
+    and write it; the last pass reads q_k, acc and (stages 2 and 3) q^n and
+    writes the next stage state; the signal reduction reads q once.
+    """
+    last = {1: "pass_x", 2: "pass_y", 3: "pass_z"}[ndim]
+    if kind == "signal":
+        return neq * esize
+    if kind == last:
+        reads_qn = (0 + 1 + 1) / 3.0
+        return (3 + reads_qn) * neq * esize
+    if kind == "pass_x":
+        return 2 * neq * esize
+    return 3 * neq * esize
+
+
+# Algorithmic FP64 operations per cell for one axis pass of the 3D two-fluid
+# system (counted from the method's formulas): cons->prim 21,
+# WENO5-JS 97 per row x 8 rows, HLLC 106 per face, flux difference and
+# volume-fraction source 30.  The stage update adds 32 per cell on the last pass.
+FLOPS_PASS_3D2F = 21 + 97 * 8 + 106 + 30
+FLOPS_STAGE_UPDATE = 32
+
+
+def time_steps(S, q, steps, warmup, cfl):
+    import torch
+    for _ in range(warmup):
+        S.step(q, cfl=cfl)
+    torch.cuda.synchronize()
+    S.set_timing(True)
+    S.get_timing()
+    stream = torch.cuda.current_stream()
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    t0.record(stream)
+    for _ in range(steps):
+        S.step(q, cfl=cfl)
+    t1.record(stream)
+    torch.cuda.synchronize()
+    ms = t0.elapsed_time(t1)
+    kinds = S.get_timing()
+    S.set_timing(False)
+    S.check()
+    return ms, kinds
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--n", type=int, default=256, help="bubble-cloud grid edge (256 = the configuration)")
+    ap.add_argument("--no-fp32", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(run with --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import workloads as W
+    from paper_2503_07953_amd.solver import Solver
+
+    torch.cuda.set_device(0)
+    t_ic = time.time()
+    case = W.bubble_cloud(args.n)
+    log(f"initial condition {case.name}: {time.time() - t_ic:.1f}s")
+    ncell = case.ncell
+    neq = case.neq
+    cfl = case.cfl
+
+    # ---------------- FP64 ----------------
+    S = Solver.from_case(case, precision="fp64")
+    q = S.prim_to_cons(S.to_device(case.w))
+    ms, kinds = time_steps(S, q, args.steps, args.warmup, cfl)
+    ms_step = ms / args.steps
+    grind = ms_step * 1e6 / (ncell * 3)
+    log(f"fp64: {ms_step:.3f} ms/step, {grind:.4f} ns/cell/stage, kinds {kinds}")
+
+    # dominant kernel roofline
+    dom = max((k for k in kinds if kinds[k][1] > 0), key=lambda k: kinds[k][0])
+    avg_ms = kinds[dom][0] / kinds[dom][1]
+    bpc = pass_bytes_per_cell(dom, neq, 8, case.ndim)
+    bytes_launch = bpc * ncell
+    achieved = bytes_launch / (avg_ms * 1e-3) / 1e9
+    flops_cell = FLOPS_PASS_3D2F + (FLOPS_STAGE_UPDATE if dom == "pass_z" else 0)
+    tflops = flops_cell * ncell / (avg_ms * 1e-3) / 1e12
+    stage_bytes = (8.0 / 3.0) * neq * 8  # per cell-stage, ideal fused path
+    roofline = {
+        "bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+        "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+        "avg_launch_ms": round(avg_ms, 5), "alg_bytes_per_cell": round(bpc, 2),
+        "fp64_tflops_alg": round(tflops, 3), "fp64_frac_alg": round(tflops / FP64_PEAK_TFLOPS, 4),
+    }
+
+    # ---------------- FP32 form ----------------
+    fp32 = None
+    if not args.no_fp32:
+        S32 = Solver.from_case(case, precision="fp32")
+        q32 = S32.prim_to_cons(S32.to_device(case.w))
+        ms32, kinds32 = time_steps(S32, q32, args.steps, args.warmup, cfl)
+        g32 = ms32 / args.steps * 1e6 / (ncell * 3)
+        a = q32.double().cpu().numpy()
+        b = q.cpu().numpy()
+        linf = [float(np.abs(a[v] - b[v]).max() / np.abs(b[v]).max()) for v in range(neq)]
+        l2 = [float(np.linalg.norm(a[v] - b[v]) / np.linalg.norm(b[v])) for v in range(neq)]
+        fp32 = {"ns_per_cell_stage": round(g32, 5), "speedup_vs_fp64": round(grind / g32, 3),
+                "steps_compared": args.warmup + args.steps,
+                "error_vs_fp64_linf": [float(f"{x:.3e}") for x in linf],
+                "error_vs_fp64_l2": [float(f"{x:.3e}") for x in l2]}
+        log(f"fp32: {g32:.4f} ns/cell/stage, speedup {grind / g32:.2f}, linf {linf}")
+        del S32, q32
+
+    # ---------------- CPU oracle on this host ----------------
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+        O = oracle.Oracle(case)
+        qh = O.prim_to_cons(case.w)
+        t0 = time.time()
+        O.step(qh, cfl=cfl)
+        t_cpu = time.time() - t0
+        threads = oracle.num_threads()
+        cpu = {"value": round(t_cpu * 1e9 / (ncell * 3), 3), "unit": "ns/cell/RK-stage", "cores": threads,
+               "kind": "oracle", "sample": f"1 SSP-RK3 step (3 RHS evaluations) of the {args.n}^3 bubble cloud, "
+                                           f"{t_cpu:.1f} s wall on {threads} OpenMP threads"}
+        log(f"cpu oracle: {cpu}")
+
+    out = {
+        "metric": METRIC, "value": round(grind, 5), "unit": "ns/cell/RK-stage", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_step, 4),
+        "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic (seeded bubble-cloud initial condition)",
+        "config": {"workload": f"3D air-water bubble cloud {args.n}^3, 64 bubbles, 100 bar pulse, "
+                               f"2 fluids / 8 rows, WENO5-JS+HLLC+SSP-RK3, CFL 0.5",
+                   "cells": ncell, "rows": neq},
+        "grind_ns_per_cell_pde_rhs": round(grind / neq, 6),
+        "hbm_frac_stage_alg": round(stage_bytes / (grind * 1e-9) / 1e9 / HBM_PEAK_GBS, 4),
+        "kernel_ms": {k: [round(v[0], 4), v[1]] for k, v in kinds.items()},
+        "roofline": roofline,
+        "fp32_form": fp32,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

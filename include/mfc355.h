@@ -1,0 +1,177 @@
+/*
+ * mfc355.h -- C ABI of the MI355X (gfx950) five-equation right-hand side.
+ *
+ * The library evaluates the semi-discrete right-hand side of the
+ * five-equation diffuse-interface model in Allaire form (arXiv 2503.07953,
+ * Sec. 2.1.1, eq. five_eqn_transport with K = 0) closed by the stiffened-gas
+ * equation of state (Sec. 2.2, eq. eos), on a uniform structured grid, and
+ * advances it with the three-stage SSP Runge-Kutta scheme (Sec. 3.4):
+ *
+ *   dq_{ijk}/dt = sum_d (F_{-1/2} - F_{+1/2})/dx_d + alpha (div u)_{ijk}
+ *
+ * (eq. eqn:rhs with s = 0 and h = -alpha), with face fluxes from WENO5-JS
+ * reconstruction of primitive variables (Sec. 3.2.1) and the HLLC solver
+ * (Sec. 3.2.2), which also returns the face velocity used for div u.
+ *
+ * Conventions for every entry point
+ * ---------------------------------
+ * Arrays: caller-owned DEVICE memory, structure-of-arrays, C order
+ *   q[v][k][j][i] (x fastest), interior cells only, element type given by
+ *   mfc_problem.precision (double for MFC_FP64, float for MFC_FP32_MIXED),
+ *   aligned to the element size.  Rows for nf fluids in D dimensions:
+ *     alpha_i rho_i (nf rows), rho u_d (D rows), rho E,
+ *     alpha_i (nf rows, only for nf == 2).
+ *   mfc_num_eqs() gives the row count.  Primitive arrays use the rows
+ *   alpha_i rho_i, u_d, p, alpha_i.  Scalars returned on the device
+ *   (dt, signal speed, sums) are always double.
+ * Ownership: the library never frees or keeps user pointers after a call
+ *   returns; the context owns only its own scratch.
+ * Streams: every call is asynchronous on `hip_stream` (a hipStream_t; NULL
+ *   is the default stream).  A context serves one stream at a time.
+ * Errors: negative return codes.  Argument, shape and alignment checks run on
+ *   the host before any HIP call.  Launch failures return MFC_ERR_HIP.  A
+ *   face state with non-positive squared sound speed or a non-finite flux
+ *   sets a device flag that mfc_check() reports as MFC_ERR_NONFINITE.
+ *   mfc_last_error() describes the last failure of a context.
+ */
+#ifndef MFC355_H
+#define MFC355_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define MFC_ABI_VERSION 1
+
+enum {
+  MFC_OK = 0,
+  MFC_ERR_ARG = -1,         /* null pointer, bad value, misaligned pointer */
+  MFC_ERR_SHAPE = -2,       /* grid sizes inconsistent with ndim or too large */
+  MFC_ERR_UNSUPPORTED = -3, /* ndim, fluid count or precision not provided */
+  MFC_ERR_HIP = -4,         /* a HIP runtime call or kernel launch failed */
+  MFC_ERR_NONFINITE = -5,   /* c^2 <= 0 or a non-finite flux was met */
+  MFC_ERR_ALLOC = -6        /* device scratch allocation failed */
+};
+
+/* Boundary conditions through three ghost layers per side (Sec. 3.3):
+ * PERIODIC wraps (both sides of an axis must be periodic); EXTRAP copies the
+ * nearest interior cell; SLIPWALL mirrors the interior with the wall-normal
+ * momentum negated. */
+enum { MFC_BC_PERIODIC = 0, MFC_BC_EXTRAP = 1, MFC_BC_SLIPWALL = 2 };
+
+/* MFC_FP64: double storage and arithmetic.
+ * MFC_FP32_MIXED: float storage, float WENO/HLLC arithmetic; double for the
+ * pressure inversion from total energy, sound and wave speeds, the stage
+ * combination, the CFL reduction and the conservation sums. */
+enum { MFC_FP64 = 0, MFC_FP32_MIXED = 1 };
+
+typedef struct {
+  int32_t abi_version; /* must equal MFC_ABI_VERSION */
+  int32_t ndim;        /* 1, 2 or 3 */
+  int32_t n[3];        /* interior cells per axis; >= 3 on active axes, 1 on unused */
+  int32_t num_fluids;  /* 1 (Euler) or 2 (five-equation model) */
+  int32_t precision;   /* MFC_FP64 or MFC_FP32_MIXED */
+  int32_t bc_lo[3];    /* MFC_BC_* per axis, low side */
+  int32_t bc_hi[3];    /* MFC_BC_* per axis, high side */
+  double dx[3];        /* uniform spacing per axis (> 0 on active axes) */
+  double gamma[2];     /* stiffened-gas gamma_i > 1 per fluid (Sec. 2.2) */
+  double pi_inf[2];    /* stiffened-gas pi_inf,i >= 0 per fluid */
+  double weno_eps;     /* WENO5-JS smoothness regularization, > 0 (1e-6) */
+} mfc_problem;
+
+typedef struct mfc_ctx mfc_ctx;
+
+/* Library and problem queries (host only, no HIP calls). */
+int mfc_abi_version(void);
+const char* mfc_status_string(int status);
+/* Row count: 2N + D + 1 for two fluids, D + 2 for one; negative on error. */
+int mfc_num_eqs(const mfc_problem* prob);
+/* Full host-side validation of a problem description; MFC_OK or an error. */
+int mfc_validate(const mfc_problem* prob);
+
+/* Create a context for `prob` on the current HIP device: validates, copies the
+ * description and allocates device scratch (two stage states, one RHS
+ * accumulator, reduction partials and flags).  *out is NULL on failure. */
+int mfc_create(const mfc_problem* prob, mfc_ctx** out);
+/* Release a context and its scratch (synchronizes the device).  NULL is a no-op. */
+int mfc_destroy(mfc_ctx* ctx);
+/* Description of the last error met by `ctx` (never NULL). */
+const char* mfc_last_error(const mfc_ctx* ctx);
+
+/* Primitive (alpha_i rho_i, u_d, p, alpha_i) -> conservative rows with the
+ * mixture rule rho E = Gamma p + Pi + rho |u|^2 / 2 (Sec. 2.1.1, 2.2).
+ * w and q may not alias. */
+int mfc_prim_to_cons(mfc_ctx* ctx, const void* w, void* q, void* hip_stream);
+/* Conservative -> primitive: u_d = (rho u_d)/rho, p = (rho E - rho|u|^2/2 - Pi)/Gamma. */
+int mfc_cons_to_prim(mfc_ctx* ctx, const void* q, void* w, void* hip_stream);
+
+/* Right-hand side L(q) of eq. eqn:rhs: rhs = sum over axes of the flux
+ * difference plus alpha (u_{+1/2} - u_{-1/2})/dx on the alpha rows.
+ * q and rhs: neq*ncell elements; they may not alias. */
+int mfc_rhs(mfc_ctx* ctx, const void* q, void* rhs, void* hip_stream);
+
+/* Largest signal speed s = max_cells sum_d (|u_d| + c)/dx_d (the time-step
+ * rule; the paper states none) written to smax_dev (device double). */
+int mfc_max_signal(mfc_ctx* ctx, const void* q, double* smax_dev, void* hip_stream);
+
+/* One SSP-RK3 step (Shu-Osher form, Sec. 3.4), in place: q holds q^n on entry
+ * and q^{n+1} on return.  Exactly one of `cfl` (> 0: dt = cfl/s computed on
+ * the device from q^n, clipped to t_remaining when t_remaining > 0) and
+ * `dt_fixed` (> 0) must be positive, else MFC_ERR_ARG.  dt_dev (device
+ * double, may be NULL) receives the dt used.  No host synchronization. */
+int mfc_step(mfc_ctx* ctx, void* q, double cfl, double dt_fixed, double t_remaining,
+             double* dt_dev, void* hip_stream);
+
+/* Conservation diagnostics: sums_dev[v] = (sum over cells of q[v]) * cell volume,
+ * neq device doubles, accumulated in double with a fixed reduction order. */
+int mfc_conserved_sums(mfc_ctx* ctx, const void* q, double* sums_dev, void* hip_stream);
+
+/* ---- Discrete adjoint (FP64 contexts only; MFC_ERR_UNSUPPORTED otherwise) ----
+ * Hand-written reverse mode of the discrete operators above (not in the paper,
+ * which has no adjoint): derivatives follow the branch the forward pass takes
+ * (wave-speed min/max ties to the first argument, HLLC region order as in the
+ * forward solver).  The first call allocates adjoint scratch in the context
+ * (about 6*neq+1 doubles per face of the largest axis plus three states).
+ * Outputs may not alias inputs.  accumulate != 0 adds to the output instead of
+ * overwriting it. */
+
+/* q_bar (+)= (dL/dq)^T rhs_bar, L the right-hand side of mfc_rhs at q. */
+int mfc_rhs_vjp(mfc_ctx* ctx, const void* q, const void* rhs_bar, void* q_bar, int accumulate,
+                void* hip_stream);
+
+/* Adjoint of one SSP-RK3 step with the fixed time step dt (a frozen-dt step,
+ * as mfc_step with dt_fixed = dt): qn_bar = (dq^{n+1}/dq^n)^T qnp1_bar.  The
+ * stage states are recomputed from q_n inside the call. */
+int mfc_step_vjp(mfc_ctx* ctx, const void* q_n, double dt, const void* qnp1_bar, void* qn_bar,
+                 void* hip_stream);
+
+/* q_bar (+)= (dw/dq)^T w_bar for the conversion of mfc_cons_to_prim at q. */
+int mfc_cons_to_prim_vjp(mfc_ctx* ctx, const void* q, const void* w_bar, void* q_bar, int accumulate,
+                         void* hip_stream);
+
+/* w_bar (+)= (dq/dw)^T q_bar for the conversion of mfc_prim_to_cons at w. */
+int mfc_prim_to_cons_vjp(mfc_ctx* ctx, const void* w, const void* q_bar, void* w_bar, int accumulate,
+                         void* hip_stream);
+
+/* Synchronize `hip_stream`, then report and clear the non-finite flag:
+ * MFC_OK or MFC_ERR_NONFINITE (or MFC_ERR_HIP if the stream failed). */
+int mfc_check(mfc_ctx* ctx, void* hip_stream);
+
+/* Diagnostics: launch timing.  While enabled, every kernel launch of
+ * mfc_step, mfc_rhs and the VJP entry points is bracketed by a pair of HIP
+ * events recorded on its own launch stream.  mfc_get_timing waits for the
+ * recorded events and returns, per launch kind
+ *   0 signal-speed reduction, 1 x pass, 2 y pass, 3 z pass, 4 adjoint passes,
+ * the summed milliseconds (ms_sum[5]) and launch counts (counts[5]) since the
+ * previous call, then starts a new interval.  Timing adds two event records
+ * per launch; it is off after mfc_create. */
+#define MFC_TIMING_KINDS 5
+int mfc_set_timing(mfc_ctx* ctx, int enable);
+int mfc_get_timing(mfc_ctx* ctx, double* ms_sum, int64_t* counts);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MFC355_H */

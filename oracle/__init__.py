@@ -81,6 +81,7 @@ def lib():
             "orc_sound_speed_sq": (ctypes.c_int, [P, dp, dp]),
             "orc_conserved_sums": (ctypes.c_int, [P, dp, dp]),
             "orc_abi_version": (ctypes.c_int, []),
+            "orc_num_threads": (ctypes.c_int, []),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -219,6 +220,10 @@ class Oracle:
         uf = ctypes.c_double()
         rc = self.L.orc_hllc(ctypes.byref(self.P), d, _dp(wl), _dp(wr), _dp(F), ctypes.byref(uf))
         return F, uf.value, rc
+
+
+def num_threads() -> int:
+    return lib().orc_num_threads()
 
 
 def weno5_js_left(f, eps=1e-6):

@@ -22,6 +22,9 @@
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 #define ORC_OK 0
 #define ORC_ERR_ARG (-1)
@@ -599,3 +602,12 @@ int orc_conserved_sums(const orc_problem* P, const double* q, double* sums) {
 }
 
 int orc_abi_version(void) { return 1; }
+
+/* OpenMP threads the parallel loops use. */
+int orc_num_threads(void) {
+#ifdef _OPENMP
+  return omp_get_max_threads();
+#else
+  return 1;
+#endif
+}

@@ -26,7 +26,7 @@ class _Sqrt(torch.autograd.Function):
 
     @staticmethod
     def forward(ctx, x):
-        y = torch.from_numpy(np.sqrt(x.detach().cpu().numpy())).to(x.device)
+        y = torch.from_numpy(np.asarray(np.sqrt(x.detach().cpu().numpy()))).to(x.device)
         ctx.save_for_backward(y)
         return y
 

@@ -1,0 +1,516 @@
+// api.hip -- the C ABI declared in include/mfc355.h: problem validation,
+// context and scratch ownership, argument checks, and the launch sequences of
+// the right-hand side, the SSP-RK3 step and the diagnostics.
+#include <stdint.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/mfc355.h"
+#include "device.h"
+#include "internal.h"
+
+// Event pairs around every launch of an entry point (diagnostics).
+struct EventTimer : mfc::PassTimer {
+  std::vector<hipEvent_t> pool;
+  size_t used = 0;
+  struct Rec {
+    int kind;
+    hipEvent_t a, b;
+  };
+  std::vector<Rec> recs;
+  hipEvent_t pending = nullptr;
+  hipError_t err = hipSuccess;
+
+  hipEvent_t get() {
+    if (used < pool.size()) return pool[used++];
+    hipEvent_t e = nullptr;
+    hipError_t r = hipEventCreate(&e);
+    if (r != hipSuccess) {
+      err = r;
+      return nullptr;
+    }
+    pool.push_back(e);
+    ++used;
+    return e;
+  }
+  void begin(int, hipStream_t s) override {
+    pending = get();
+    if (pending) (void)hipEventRecord(pending, s);
+  }
+  void end(int kind, hipStream_t s) override {
+    hipEvent_t e = get();
+    if (!e || !pending) return;
+    (void)hipEventRecord(e, s);
+    recs.push_back({kind, pending, e});
+    pending = nullptr;
+  }
+  hipError_t collect(double* ms, int64_t* cnt) {
+    for (int k = 0; k < mfc::KIND_COUNT; ++k) {
+      ms[k] = 0.0;
+      cnt[k] = 0;
+    }
+    hipError_t r = err;
+    for (const Rec& x : recs) {
+      hipError_t e = hipEventSynchronize(x.b);
+      float t = 0.f;
+      if (e == hipSuccess) e = hipEventElapsedTime(&t, x.a, x.b);
+      if (e != hipSuccess) {
+        r = e;
+        continue;
+      }
+      ms[x.kind] += t;
+      cnt[x.kind] += 1;
+    }
+    recs.clear();
+    used = 0;
+    err = hipSuccess;
+    return r;
+  }
+  ~EventTimer() override {
+    for (hipEvent_t e : pool) (void)hipEventDestroy(e);
+  }
+};
+
+struct mfc_ctx {
+  mfc_problem prob;
+  mfc::Params pm;
+  int neq;
+  long long ncell;
+  size_t esize;       // bytes per element of q
+  void* acc;          // RHS accumulator (neq*ncell elements)
+  void* q1;           // stage state 1
+  void* q2;           // stage state 2
+  double* scal;       // [0] smax, [1] dt
+  double* partial;    // reduction partials (kReduceBlocks * neq)
+  int* flag;          // non-finite flag
+  int device;
+  std::string err;
+  EventTimer* timer;  // non-null while timing is enabled
+  // adjoint scratch (allocated on the first adjoint call)
+  mfc::VjpScratch vjp;
+  double* vbuf;       // L^T v
+  double* b1;         // stage cotangents
+  double* b2;
+};
+
+namespace {
+
+int fail(mfc_ctx* c, int code, const char* msg) {
+  if (c) c->err = msg;
+  return code;
+}
+
+int hip_fail(mfc_ctx* c, hipError_t e, const char* where) {
+  if (c) {
+    c->err = std::string(where) + ": " + hipGetErrorString(e);
+  }
+  return MFC_ERR_HIP;
+}
+
+int ensure_vjp_scratch(mfc_ctx* c) {
+  if (c->vjp.G) return MFC_OK;
+  long long maxfaces = 0, maxlines = 0;
+  for (int d = 0; d < c->prob.ndim; ++d) {
+    const long long lines = c->ncell / c->prob.n[d];
+    const long long faces = lines * (c->prob.n[d] + 1);
+    if (faces > maxfaces) maxfaces = faces;
+    if (lines > maxlines) maxlines = lines;
+  }
+  const size_t bb_stride = (size_t)6 * c->neq * (size_t)maxlines;
+  const size_t state = (size_t)c->neq * (size_t)c->ncell * sizeof(double);
+  bool ok = hipMalloc((void**)&c->vjp.G, (size_t)6 * c->neq * (size_t)maxfaces * sizeof(double)) == hipSuccess &&
+            hipMalloc((void**)&c->vjp.UF, (size_t)maxfaces * sizeof(double)) == hipSuccess &&
+            hipMalloc((void**)&c->vjp.BB, bb_stride * 3 * sizeof(double)) == hipSuccess &&
+            hipMalloc((void**)&c->vbuf, state) == hipSuccess && hipMalloc((void**)&c->b1, state) == hipSuccess &&
+            hipMalloc((void**)&c->b2, state) == hipSuccess;
+  c->vjp.bb_stride = bb_stride;
+  if (!ok) {
+    (void)hipGetLastError();
+    c->err = "adjoint scratch allocation failed";
+    return MFC_ERR_ALLOC;
+  }
+  return MFC_OK;
+}
+
+bool aligned(const void* p, size_t a) { return (reinterpret_cast<uintptr_t>(p) % a) == 0; }
+
+int check_array(mfc_ctx* c, const void* p, const char* name) {
+  if (!p) {
+    c->err = std::string("null pointer: ") + name;
+    return MFC_ERR_ARG;
+  }
+  if (!aligned(p, c->esize)) {
+    c->err = std::string("misaligned pointer: ") + name;
+    return MFC_ERR_ARG;
+  }
+  return MFC_OK;
+}
+
+mfc::Params make_params(const mfc_problem& p) {
+  mfc::Params pm;
+  memset(&pm, 0, sizeof(pm));
+  for (int d = 0; d < 3; ++d) {
+    pm.n[d] = p.n[d];
+    pm.bc_lo[d] = p.bc_lo[d];
+    pm.bc_hi[d] = p.bc_hi[d];
+    pm.inv_dx[d] = (d < p.ndim) ? 1.0 / p.dx[d] : 0.0;
+  }
+  for (int i = 0; i < 2; ++i) {
+    const int k = (i < p.num_fluids) ? i : 0;
+    pm.G[i] = 1.0 / (p.gamma[k] - 1.0);
+    pm.P[i] = p.gamma[k] * p.pi_inf[k] / (p.gamma[k] - 1.0);
+  }
+  pm.eps = p.weno_eps;
+  pm.ncell = (long long)p.n[0] * p.n[1] * p.n[2];
+  return pm;
+}
+
+}  // namespace
+
+extern "C" {
+
+int mfc_abi_version(void) { return MFC_ABI_VERSION; }
+
+const char* mfc_status_string(int s) {
+  switch (s) {
+    case MFC_OK: return "ok";
+    case MFC_ERR_ARG: return "invalid argument";
+    case MFC_ERR_SHAPE: return "invalid shape";
+    case MFC_ERR_UNSUPPORTED: return "unsupported configuration";
+    case MFC_ERR_HIP: return "HIP error";
+    case MFC_ERR_NONFINITE: return "non-finite state or non-positive squared sound speed";
+    case MFC_ERR_ALLOC: return "device allocation failed";
+    default: return "unknown status";
+  }
+}
+
+int mfc_num_eqs(const mfc_problem* p) {
+  if (!p) return MFC_ERR_ARG;
+  if (p->ndim < 1 || p->ndim > 3) return MFC_ERR_UNSUPPORTED;
+  if (p->num_fluids != 1 && p->num_fluids != 2) return MFC_ERR_UNSUPPORTED;
+  return p->num_fluids + p->ndim + 1 + (p->num_fluids == 2 ? 2 : 0);
+}
+
+int mfc_validate(const mfc_problem* p) {
+  if (!p) return MFC_ERR_ARG;
+  if (p->abi_version != MFC_ABI_VERSION) return MFC_ERR_ARG;
+  if (p->ndim < 1 || p->ndim > 3) return MFC_ERR_UNSUPPORTED;
+  if (p->num_fluids != 1 && p->num_fluids != 2) return MFC_ERR_UNSUPPORTED;
+  if (p->precision != MFC_FP64 && p->precision != MFC_FP32_MIXED) return MFC_ERR_UNSUPPORTED;
+  long long ncell = 1;
+  for (int d = 0; d < 3; ++d) {
+    if (d < p->ndim) {
+      if (p->n[d] < 3) return MFC_ERR_SHAPE;
+      if (!(p->dx[d] > 0.0) || !(p->dx[d] < 1e300)) return MFC_ERR_ARG;
+      if (p->bc_lo[d] < 0 || p->bc_lo[d] > 2 || p->bc_hi[d] < 0 || p->bc_hi[d] > 2) return MFC_ERR_ARG;
+      if ((p->bc_lo[d] == MFC_BC_PERIODIC) != (p->bc_hi[d] == MFC_BC_PERIODIC)) return MFC_ERR_ARG;
+    } else if (p->n[d] != 1) {
+      return MFC_ERR_SHAPE;
+    }
+    ncell *= p->n[d];
+  }
+  // grid launch limits: y and z extents index grid dimensions directly
+  if (p->n[1] > 65535 * 16 || p->n[2] > 65535 * 16) return MFC_ERR_SHAPE;
+  if (ncell > (1LL << 40)) return MFC_ERR_SHAPE;
+  for (int i = 0; i < p->num_fluids; ++i)
+    if (!(p->gamma[i] > 1.0) || !(p->pi_inf[i] >= 0.0) || !(p->pi_inf[i] < 1e300)) return MFC_ERR_ARG;
+  if (!(p->weno_eps > 0.0)) return MFC_ERR_ARG;
+  return MFC_OK;
+}
+
+int mfc_create(const mfc_problem* p, mfc_ctx** out) {
+  if (!out) return MFC_ERR_ARG;
+  *out = nullptr;
+  int v = mfc_validate(p);
+  if (v != MFC_OK) return v;
+  mfc_ctx* c = new mfc_ctx();
+  c->prob = *p;
+  c->pm = make_params(*p);
+  c->neq = mfc_num_eqs(p);
+  c->ncell = c->pm.ncell;
+  c->esize = (p->precision == MFC_FP64) ? sizeof(double) : sizeof(float);
+  c->acc = c->q1 = c->q2 = nullptr;
+  c->scal = c->partial = nullptr;
+  c->flag = nullptr;
+  c->timer = nullptr;
+  c->vjp = mfc::VjpScratch{nullptr, nullptr, nullptr, 0};
+  c->vbuf = c->b1 = c->b2 = nullptr;
+  if (hipGetDevice(&c->device) != hipSuccess) {
+    delete c;
+    return MFC_ERR_HIP;
+  }
+  const size_t bytes = (size_t)c->neq * (size_t)c->ncell * c->esize;
+  bool ok = hipMalloc(&c->acc, bytes) == hipSuccess && hipMalloc(&c->q1, bytes) == hipSuccess &&
+            hipMalloc(&c->q2, bytes) == hipSuccess &&
+            hipMalloc((void**)&c->scal, 4 * sizeof(double)) == hipSuccess &&
+            hipMalloc((void**)&c->partial, (size_t)mfc::kReduceBlocks * 8 * sizeof(double)) == hipSuccess &&
+            hipMalloc((void**)&c->flag, sizeof(int)) == hipSuccess;
+  if (ok) ok = hipMemset(c->flag, 0, sizeof(int)) == hipSuccess;
+  if (ok) ok = hipMemset(c->scal, 0, 4 * sizeof(double)) == hipSuccess;
+  if (!ok) {
+    (void)hipGetLastError();
+    mfc_destroy(c);
+    return MFC_ERR_ALLOC;
+  }
+  *out = c;
+  return MFC_OK;
+}
+
+int mfc_destroy(mfc_ctx* c) {
+  if (!c) return MFC_OK;
+  (void)hipDeviceSynchronize();
+  if (c->acc) (void)hipFree(c->acc);
+  if (c->q1) (void)hipFree(c->q1);
+  if (c->q2) (void)hipFree(c->q2);
+  if (c->scal) (void)hipFree(c->scal);
+  if (c->partial) (void)hipFree(c->partial);
+  if (c->flag) (void)hipFree(c->flag);
+  if (c->vjp.G) (void)hipFree(c->vjp.G);
+  if (c->vjp.UF) (void)hipFree(c->vjp.UF);
+  if (c->vjp.BB) (void)hipFree(c->vjp.BB);
+  if (c->vbuf) (void)hipFree(c->vbuf);
+  if (c->b1) (void)hipFree(c->b1);
+  if (c->b2) (void)hipFree(c->b2);
+  delete c->timer;
+  delete c;
+  return MFC_OK;
+}
+
+const char* mfc_last_error(const mfc_ctx* c) {
+  if (!c) return "null context";
+  return c->err.c_str();
+}
+
+#define MFC_DISPATCH_REAL(c, CALL_D, CALL_F) \
+  ((c)->prob.precision == MFC_FP64 ? (CALL_D) : (CALL_F))
+
+int mfc_prim_to_cons(mfc_ctx* c, const void* w, void* q, void* stream) {
+  if (!c) return MFC_ERR_ARG;
+  int r;
+  if ((r = check_array(c, w, "w")) || (r = check_array(c, q, "q"))) return r;
+  if (w == q) return fail(c, MFC_ERR_ARG, "w and q alias");
+  hipStream_t s = (hipStream_t)stream;
+  hipError_t e = MFC_DISPATCH_REAL(
+      c, mfc::launch_convert<double>(c->prob.num_fluids, c->prob.ndim, true, c->pm, (const double*)w, (double*)q, s),
+      mfc::launch_convert<float>(c->prob.num_fluids, c->prob.ndim, true, c->pm, (const float*)w, (float*)q, s));
+  return e == hipSuccess ? MFC_OK : hip_fail(c, e, "prim_to_cons");
+}
+
+int mfc_cons_to_prim(mfc_ctx* c, const void* q, void* w, void* stream) {
+  if (!c) return MFC_ERR_ARG;
+  int r;
+  if ((r = check_array(c, w, "w")) || (r = check_array(c, q, "q"))) return r;
+  if (w == q) return fail(c, MFC_ERR_ARG, "w and q alias");
+  hipStream_t s = (hipStream_t)stream;
+  hipError_t e = MFC_DISPATCH_REAL(
+      c, mfc::launch_convert<double>(c->prob.num_fluids, c->prob.ndim, false, c->pm, (const double*)q, (double*)w, s),
+      mfc::launch_convert<float>(c->prob.num_fluids, c->prob.ndim, false, c->pm, (const float*)q, (float*)w, s));
+  return e == hipSuccess ? MFC_OK : hip_fail(c, e, "cons_to_prim");
+}
+
+int mfc_rhs(mfc_ctx* c, const void* q, void* rhs, void* stream) {
+  if (!c) return MFC_ERR_ARG;
+  int r;
+  if ((r = check_array(c, q, "q")) || (r = check_array(c, rhs, "rhs"))) return r;
+  if (q == rhs) return fail(c, MFC_ERR_ARG, "q and rhs alias");
+  hipStream_t s = (hipStream_t)stream;
+  mfc::StageArgs st{0, 0.0, nullptr};
+  hipError_t e = MFC_DISPATCH_REAL(
+      c,
+      mfc::launch_rhs<double>(c->prob.num_fluids, c->prob.ndim, c->pm, (const double*)q, (double*)rhs, nullptr,
+                              nullptr, st, false, c->flag, s, c->timer),
+      mfc::launch_rhs<float>(c->prob.num_fluids, c->prob.ndim, c->pm, (const float*)q, (float*)rhs, nullptr,
+                             nullptr, st, false, c->flag, s, c->timer));
+  return e == hipSuccess ? MFC_OK : hip_fail(c, e, "rhs");
+}
+
+int mfc_max_signal(mfc_ctx* c, const void* q, double* smax_dev, void* stream) {
+  if (!c) return MFC_ERR_ARG;
+  int r;
+  if ((r = check_array(c, q, "q"))) return r;
+  if (!smax_dev || !aligned(smax_dev, sizeof(double))) return fail(c, MFC_ERR_ARG, "bad smax pointer");
+  hipStream_t s = (hipStream_t)stream;
+  hipError_t e = MFC_DISPATCH_REAL(
+      c,
+      mfc::launch_max_signal<double>(c->prob.num_fluids, c->prob.ndim, c->pm, (const double*)q, c->partial,
+                                     smax_dev, 0.0, 0.0, nullptr, nullptr, c->flag, s),
+      mfc::launch_max_signal<float>(c->prob.num_fluids, c->prob.ndim, c->pm, (const float*)q, c->partial,
+                                    smax_dev, 0.0, 0.0, nullptr, nullptr, c->flag, s));
+  return e == hipSuccess ? MFC_OK : hip_fail(c, e, "max_signal");
+}
+
+}  // extern "C"
+
+namespace {
+template <typename Real>
+hipError_t step_t(mfc_ctx* c, Real* q, double cfl, double dt_fixed, double t_remaining, double* dt_user,
+                  hipStream_t s) {
+  const int nf = c->prob.num_fluids, nd = c->prob.ndim;
+  hipError_t e;
+  mfc::StageArgs st{1, dt_fixed, nullptr};
+  if (cfl > 0.0) {
+    if (c->timer) c->timer->begin(mfc::KIND_SIGNAL, s);
+    e = mfc::launch_max_signal<Real>(nf, nd, c->pm, q, c->partial, &c->scal[0], cfl, t_remaining, &c->scal[1],
+                                     dt_user, c->flag, s);
+    if (c->timer) c->timer->end(mfc::KIND_SIGNAL, s);
+    if (e != hipSuccess) return e;
+    st.dt_ptr = &c->scal[1];
+  } else if (dt_user) {
+    e = mfc::launch_set_scalar(dt_user, dt_fixed, s);
+    if (e != hipSuccess) return e;
+  }
+  Real* q1 = (Real*)c->q1;
+  Real* q2 = (Real*)c->q2;
+  Real* acc = (Real*)c->acc;
+  st.stage = 1;
+  e = mfc::launch_rhs<Real>(nf, nd, c->pm, q, acc, q, q1, st, true, c->flag, s, c->timer);
+  if (e != hipSuccess) return e;
+  st.stage = 2;
+  e = mfc::launch_rhs<Real>(nf, nd, c->pm, q1, acc, q, q2, st, true, c->flag, s, c->timer);
+  if (e != hipSuccess) return e;
+  st.stage = 3;
+  e = mfc::launch_rhs<Real>(nf, nd, c->pm, q2, acc, q, q, st, true, c->flag, s, c->timer);
+  return e;
+}
+}  // namespace
+
+extern "C" {
+
+int mfc_step(mfc_ctx* c, void* q, double cfl, double dt_fixed, double t_remaining, double* dt_dev,
+             void* stream) {
+  if (!c) return MFC_ERR_ARG;
+  int r;
+  if ((r = check_array(c, q, "q"))) return r;
+  if ((cfl > 0.0) == (dt_fixed > 0.0)) return fail(c, MFC_ERR_ARG, "exactly one of cfl and dt_fixed must be > 0");
+  if (!(cfl < 1e300) || !(dt_fixed < 1e300) || t_remaining != t_remaining)
+    return fail(c, MFC_ERR_ARG, "non-finite step argument");
+  if (dt_dev && !aligned(dt_dev, sizeof(double))) return fail(c, MFC_ERR_ARG, "misaligned dt pointer");
+  hipStream_t s = (hipStream_t)stream;
+  hipError_t e = MFC_DISPATCH_REAL(c, step_t<double>(c, (double*)q, cfl, dt_fixed, t_remaining, dt_dev, s),
+                                   step_t<float>(c, (float*)q, cfl, dt_fixed, t_remaining, dt_dev, s));
+  return e == hipSuccess ? MFC_OK : hip_fail(c, e, "step");
+}
+
+int mfc_conserved_sums(mfc_ctx* c, const void* q, double* sums_dev, void* stream) {
+  if (!c) return MFC_ERR_ARG;
+  int r;
+  if ((r = check_array(c, q, "q"))) return r;
+  if (!sums_dev || !aligned(sums_dev, sizeof(double))) return fail(c, MFC_ERR_ARG, "bad sums pointer");
+  double vol = 1.0;
+  for (int d = 0; d < c->prob.ndim; ++d) vol = vol * c->prob.dx[d];
+  hipStream_t s = (hipStream_t)stream;
+  hipError_t e = MFC_DISPATCH_REAL(
+      c, mfc::launch_sums<double>(c->neq, c->pm, (const double*)q, vol, c->partial, sums_dev, s),
+      mfc::launch_sums<float>(c->neq, c->pm, (const float*)q, vol, c->partial, sums_dev, s));
+  return e == hipSuccess ? MFC_OK : hip_fail(c, e, "conserved_sums");
+}
+
+int mfc_rhs_vjp(mfc_ctx* c, const void* q, const void* rhs_bar, void* q_bar, int accumulate, void* stream) {
+  if (!c) return MFC_ERR_ARG;
+  if (c->prob.precision != MFC_FP64) return fail(c, MFC_ERR_UNSUPPORTED, "adjoint entry points are FP64 only");
+  int r;
+  if ((r = check_array(c, q, "q")) || (r = check_array(c, rhs_bar, "rhs_bar")) || (r = check_array(c, q_bar, "q_bar")))
+    return r;
+  if (q_bar == q || q_bar == rhs_bar) return fail(c, MFC_ERR_ARG, "q_bar aliases an input");
+  if ((r = ensure_vjp_scratch(c))) return r;
+  hipError_t e = mfc::launch_rhs_vjp(c->prob.num_fluids, c->prob.ndim, c->pm, (const double*)q,
+                                     (const double*)rhs_bar, (double*)q_bar, c->vjp, accumulate != 0,
+                                     (hipStream_t)stream, c->timer);
+  return e == hipSuccess ? MFC_OK : hip_fail(c, e, "rhs_vjp");
+}
+
+int mfc_step_vjp(mfc_ctx* c, const void* q_n, double dt, const void* qnp1_bar, void* qn_bar, void* stream) {
+  if (!c) return MFC_ERR_ARG;
+  if (c->prob.precision != MFC_FP64) return fail(c, MFC_ERR_UNSUPPORTED, "adjoint entry points are FP64 only");
+  int r;
+  if ((r = check_array(c, q_n, "q_n")) || (r = check_array(c, qnp1_bar, "qnp1_bar")) ||
+      (r = check_array(c, qn_bar, "qn_bar")))
+    return r;
+  if (!(dt > 0.0) || !(dt < 1e300)) return fail(c, MFC_ERR_ARG, "dt must be positive and finite");
+  if (qn_bar == q_n || qn_bar == qnp1_bar) return fail(c, MFC_ERR_ARG, "qn_bar aliases an input");
+  if ((r = ensure_vjp_scratch(c))) return r;
+  hipStream_t s = (hipStream_t)stream;
+  const int nf = c->prob.num_fluids, nd = c->prob.ndim;
+  const double* qn = (const double*)q_n;
+  double* q1 = (double*)c->q1;
+  double* q2 = (double*)c->q2;
+  double* acc = (double*)c->acc;
+  const long long n = (long long)c->neq * c->ncell;
+  // recompute the stage states with the same dt
+  mfc::StageArgs st{1, dt, nullptr};
+  hipError_t e = mfc::launch_rhs<double>(nf, nd, c->pm, qn, acc, qn, q1, st, true, c->flag, s, c->timer);
+  st.stage = 2;
+  if (e == hipSuccess) e = mfc::launch_rhs<double>(nf, nd, c->pm, q1, acc, qn, q2, st, true, c->flag, s, c->timer);
+  // reverse sweep
+  if (e == hipSuccess)
+    e = mfc::launch_rhs_vjp(nf, nd, c->pm, q2, (const double*)qnp1_bar, c->vbuf, c->vjp, false, s, c->timer);
+  if (e == hipSuccess)
+    e = mfc::launch_adj_stage(3, n, dt, (const double*)qnp1_bar, c->vbuf, c->b2, (double*)qn_bar, s);
+  if (e == hipSuccess) e = mfc::launch_rhs_vjp(nf, nd, c->pm, q1, c->b2, c->vbuf, c->vjp, false, s, c->timer);
+  if (e == hipSuccess) e = mfc::launch_adj_stage(2, n, dt, c->b2, c->vbuf, c->b1, (double*)qn_bar, s);
+  if (e == hipSuccess) e = mfc::launch_rhs_vjp(nf, nd, c->pm, qn, c->b1, c->vbuf, c->vjp, false, s, c->timer);
+  if (e == hipSuccess) e = mfc::launch_adj_stage(1, n, dt, c->b1, c->vbuf, nullptr, (double*)qn_bar, s);
+  return e == hipSuccess ? MFC_OK : hip_fail(c, e, "step_vjp");
+}
+
+int mfc_cons_to_prim_vjp(mfc_ctx* c, const void* q, const void* w_bar, void* q_bar, int accumulate, void* stream) {
+  if (!c) return MFC_ERR_ARG;
+  if (c->prob.precision != MFC_FP64) return fail(c, MFC_ERR_UNSUPPORTED, "adjoint entry points are FP64 only");
+  int r;
+  if ((r = check_array(c, q, "q")) || (r = check_array(c, w_bar, "w_bar")) || (r = check_array(c, q_bar, "q_bar")))
+    return r;
+  if (q_bar == q || q_bar == w_bar) return fail(c, MFC_ERR_ARG, "q_bar aliases an input");
+  hipError_t e = mfc::launch_convert_vjp(c->prob.num_fluids, c->prob.ndim, false, c->pm, (const double*)q,
+                                         (const double*)w_bar, (double*)q_bar, accumulate != 0, (hipStream_t)stream);
+  return e == hipSuccess ? MFC_OK : hip_fail(c, e, "cons_to_prim_vjp");
+}
+
+int mfc_prim_to_cons_vjp(mfc_ctx* c, const void* w, const void* q_bar, void* w_bar, int accumulate, void* stream) {
+  if (!c) return MFC_ERR_ARG;
+  if (c->prob.precision != MFC_FP64) return fail(c, MFC_ERR_UNSUPPORTED, "adjoint entry points are FP64 only");
+  int r;
+  if ((r = check_array(c, w, "w")) || (r = check_array(c, q_bar, "q_bar")) || (r = check_array(c, w_bar, "w_bar")))
+    return r;
+  if (w_bar == w || w_bar == q_bar) return fail(c, MFC_ERR_ARG, "w_bar aliases an input");
+  hipError_t e = mfc::launch_convert_vjp(c->prob.num_fluids, c->prob.ndim, true, c->pm, (const double*)w,
+                                         (const double*)q_bar, (double*)w_bar, accumulate != 0, (hipStream_t)stream);
+  return e == hipSuccess ? MFC_OK : hip_fail(c, e, "prim_to_cons_vjp");
+}
+
+int mfc_set_timing(mfc_ctx* c, int enable) {
+  if (!c) return MFC_ERR_ARG;
+  if (enable && !c->timer) c->timer = new EventTimer();
+  if (!enable && c->timer) {
+    delete c->timer;
+    c->timer = nullptr;
+  }
+  return MFC_OK;
+}
+
+int mfc_get_timing(mfc_ctx* c, double* ms_sum, int64_t* counts) {
+  if (!c || !ms_sum || !counts) return MFC_ERR_ARG;
+  if (!c->timer) return fail(c, MFC_ERR_ARG, "timing is not enabled");
+  hipError_t e = c->timer->collect(ms_sum, counts);
+  return e == hipSuccess ? MFC_OK : hip_fail(c, e, "get_timing");
+}
+
+int mfc_check(mfc_ctx* c, void* stream) {
+  if (!c) return MFC_ERR_ARG;
+  hipStream_t s = (hipStream_t)stream;
+  hipError_t e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return hip_fail(c, e, "check: stream");
+  int h = 0;
+  e = hipMemcpy(&h, c->flag, sizeof(int), hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return hip_fail(c, e, "check: flag");
+  if (h) {
+    e = hipMemset(c->flag, 0, sizeof(int));
+    if (e != hipSuccess) return hip_fail(c, e, "check: reset");
+    return fail(c, MFC_ERR_NONFINITE, "non-finite flux or c^2 <= 0 met");
+  }
+  return MFC_OK;
+}
+
+}  // extern "C"

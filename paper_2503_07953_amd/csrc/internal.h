@@ -1,0 +1,70 @@
+// internal.h -- host-side declarations shared by the library's translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "device.h"
+
+namespace mfc {
+
+// Output mode of an axis pass.
+enum { MODE_WRITE = 0, MODE_ACC = 1, MODE_STEP = 2 };
+
+// Stage description for the fused SSP-RK3 combination.
+struct StageArgs {
+  int stage;              // 1, 2 or 3
+  double dt;              // used when dt_ptr is null
+  const double* dt_ptr;   // device dt (CFL steps)
+};
+
+// Kinds of timed launches (see mfc_set_timing).
+enum { KIND_SIGNAL = 0, KIND_PASS_X = 1, KIND_PASS_Y = 2, KIND_PASS_Z = 3, KIND_VJP = 4, KIND_COUNT = 5 };
+
+// Optional hook that brackets every launch of an entry point with events on
+// the launch stream.
+struct PassTimer {
+  virtual void begin(int kind, hipStream_t s) = 0;
+  virtual void end(int kind, hipStream_t s) = 0;
+  virtual ~PassTimer() {}
+};
+
+// Number of blocks of the fixed-shape reductions (partials buffer length).
+constexpr int kReduceBlocks = 1024;
+constexpr int kReduceThreads = 256;
+
+template <typename Real>
+hipError_t launch_rhs(int nf, int ndim, const Params& pm, const Real* qk, Real* acc, const Real* qn,
+                      Real* qout, StageArgs st, bool final_step, int* flag, hipStream_t s,
+                      PassTimer* tm = nullptr);
+
+template <typename Real>
+hipError_t launch_max_signal(int nf, int ndim, const Params& pm, const Real* q, double* partial,
+                             double* smax_out, double cfl, double t_remaining, double* dt_out,
+                             double* dt_user, int* flag, hipStream_t s);
+
+template <typename Real>
+hipError_t launch_sums(int neq, const Params& pm, const Real* q, double vol, double* partial,
+                       double* sums_out, hipStream_t s);
+
+template <typename Real>
+hipError_t launch_convert(int nf, int ndim, bool to_cons, const Params& pm, const Real* in, Real* out,
+                          hipStream_t s);
+
+hipError_t launch_set_scalar(double* dst, double value, hipStream_t s);
+
+// Scratch of the adjoint passes (owned by the context, allocated on first use).
+struct VjpScratch {
+  double* G;          // per-face primitive cotangents of the 6 stencil positions
+  double* UF;         // per-face forward face velocity
+  double* BB;         // ghost-cell cotangents, 2 sides x 3 layers x rows x lines, per axis
+  size_t bb_stride;   // doubles per axis in BB
+};
+
+hipError_t launch_rhs_vjp(int nf, int ndim, const Params& pm, const double* q, const double* rbar, double* qbar,
+                          const VjpScratch& sc, bool accumulate, hipStream_t s, PassTimer* tm);
+hipError_t launch_convert_vjp(int nf, int ndim, bool to_cons, const Params& pm, const double* x, const double* ybar,
+                              double* xbar, bool accumulate, hipStream_t s);
+hipError_t launch_adj_stage(int which, long long n, double dt, const double* x, const double* v, double* out,
+                            double* qnb, hipStream_t s);
+
+}  // namespace mfc

@@ -1,0 +1,294 @@
+// sweep.hip -- one fused pass per grid axis of the five-equation RHS.
+//
+// A pass over axis DIR does, for a tile of cells, in one kernel:
+//   (a) load the conservative state of the tile plus three ghost/halo cells on
+//       each side along DIR (ghost layers by index remap, Sec. 3.3), convert it
+//       to primitive variables (double pressure inversion) and stage it in LDS;
+//   (b) WENO5-JS at every reconstruction centre of the tile (Sec. 3.2.1):
+//       the left-biased value at c+1/2 and the right-biased value at c-1/2;
+//   (c) HLLC at every face between two centres (Sec. 3.2.2): flux and face
+//       velocity;
+//   (d) the axis contribution of eq. eqn:rhs for every output cell:
+//       (F_{-1/2} - F_{+1/2})/dx plus alpha (u_{+1/2} - u_{-1/2})/dx on the
+//       volume-fraction rows, which is written to the RHS accumulator, added
+//       to it, or (on the last axis of an SSP-RK3 stage) combined with the
+//       stage states into the next stage state.
+// Reconstructed states, fluxes and face velocities live only in registers
+// and LDS; HBM sees one read of the stage state (plus halos), the RHS
+// accumulator round trip and the stage combination.
+//
+// Tile shapes (wave64): along x the centres of a tile are the 64 lanes of a
+// wave, one wave per x-row, 4 rows per block; along y and z, 32 x-lanes by 16
+// centres along the sweep axis (512 threads).  Every access to q is to x-
+// contiguous runs, so all three passes read HBM coalesced without any
+// transposition of the state.
+#include "device.h"
+#include "internal.h"
+
+namespace mfc {
+
+template <int DIR, int D>
+struct Tile {
+  // TA: reconstruction centres per tile along the sweep axis (outputs TA - 2)
+  // TB: independent lines across the sweep axis
+  static constexpr int TA = (DIR == 0) ? 64 : 16;
+  static constexpr int TB = (DIR == 0) ? ((D == 1) ? 1 : 4) : 32;
+  static constexpr int NT = TA * TB;
+  static constexpr int OUT = TA - 2;
+  static constexpr int SA = TA + 4;  // LDS slots along the sweep axis
+};
+
+// LDS index of (row v, slot s along the sweep axis, line b).
+template <int DIR, int D>
+__device__ __forceinline__ int lds_index(int v, int s, int b) {
+  using TL = Tile<DIR, D>;
+  if constexpr (DIR == 0)
+    return (v * TL::TB + b) * TL::SA + s;
+  else
+    return (v * TL::SA + s) * TL::TB + b;
+}
+
+template <int NF, int D, int DIR, typename Real, int MODE>
+__global__ __launch_bounds__((Tile<DIR, D>::NT)) void sweep_kernel(Params pm, const Real* __restrict__ qk,
+                                                                 Real* __restrict__ acc,
+                                                                 const Real* __restrict__ qn,
+                                                                 Real* __restrict__ qout, StageArgs st,
+                                                                 int* __restrict__ flag) {
+  using R = Rows<NF, D>;
+  using TL = Tile<DIR, D>;
+  constexpr int NEQ = R::NEQ;
+  __shared__ Real sh[(NEQ + 1) * TL::SA * TL::TB];
+
+  const int nx = pm.n[0], ny = pm.n[1];
+  const int nd = pm.n[DIR];
+  const long long nc = pm.ncell;
+  const int tid = threadIdx.y * blockDim.x + threadIdx.x;
+
+  // tile origin (first output cell along DIR) and the fixed coordinates
+  int a, b, org, cx = 0, cy = 0, cz = 0;
+  if constexpr (DIR == 0) {
+    a = threadIdx.x;
+    b = threadIdx.y;
+    org = blockIdx.x * TL::OUT;
+    cy = blockIdx.y * TL::TB;  // + line
+    cz = blockIdx.z;
+  } else if constexpr (DIR == 1) {
+    b = threadIdx.x;
+    a = threadIdx.y;
+    cx = blockIdx.x * TL::TB;
+    org = blockIdx.y * TL::OUT;
+    cz = blockIdx.z;
+  } else {
+    b = threadIdx.x;
+    a = threadIdx.y;
+    cx = blockIdx.x * TL::TB;
+    cy = blockIdx.y;
+    org = blockIdx.z * TL::OUT;
+  }
+
+  // ---- (a) load + convert the tile and its halo into LDS -------------------
+  for (int L = tid; L < TL::SA * TL::TB; L += TL::NT) {
+    int s, bb;
+    if constexpr (DIR == 0) {
+      bb = L / TL::SA;
+      s = L - bb * TL::SA;
+    } else {
+      s = L / TL::TB;
+      bb = L - s * TL::TB;
+    }
+    const int pos = org - 3 + s;
+    int ix = cx, iy = cy, iz = cz;
+    bool inb;
+    if constexpr (DIR == 0) {
+      iy += bb;
+      inb = iy < ny;
+    } else {
+      ix += bb;
+      inb = ix < nx;
+    }
+    if (!inb || pos > nd + 2) continue;
+    bool flip;
+    const int g = ghost_index(pos, nd, pm.bc_lo[DIR], pm.bc_hi[DIR], flip);
+    if constexpr (DIR == 0) ix = g;
+    else if constexpr (DIR == 1) iy = g;
+    else iz = g;
+    const long long cell = ((long long)iz * ny + iy) * nx + ix;
+    double U[NEQ], W[NEQ];
+#pragma unroll
+    for (int v = 0; v < NEQ; ++v) U[v] = double(qk[v * nc + cell]);
+    if (flip) U[R::MOM + DIR] = -U[R::MOM + DIR];
+    cons_to_prim<NF, D>(pm, U, W);
+#pragma unroll
+    for (int v = 0; v < NEQ; ++v) sh[lds_index<DIR, D>(v, s, bb)] = Real(W[v]);
+  }
+  __syncthreads();
+
+  // this thread's reconstruction centre and line
+  const int c = org - 1 + a;
+  int ox = cx, oy = cy, oz = cz;
+  bool line_ok;
+  if constexpr (DIR == 0) {
+    oy += b;
+    line_ok = oy < ny;
+  } else {
+    ox += b;
+    line_ok = ox < nx;
+  }
+  const bool centre_ok = line_ok && c <= nd;
+
+  // ---- (b) WENO5-JS at centre c -----------------------------------------------
+  Real WLc[NEQ], WRc[NEQ];  // value at c+1/2 (left-biased) and at c-1/2 (right-biased)
+  Real alpha_cell[2] = {Real(0), Real(0)};
+  if (centre_ok) {
+    const Real eps = Real(pm.eps);
+#pragma unroll
+    for (int v = 0; v < NEQ; ++v) {
+      const Real f0 = sh[lds_index<DIR, D>(v, a + 0, b)];
+      const Real f1 = sh[lds_index<DIR, D>(v, a + 1, b)];
+      const Real f2 = sh[lds_index<DIR, D>(v, a + 2, b)];
+      const Real f3 = sh[lds_index<DIR, D>(v, a + 3, b)];
+      const Real f4 = sh[lds_index<DIR, D>(v, a + 4, b)];
+      weno5_js(f0, f1, f2, f3, f4, eps, WLc[v], WRc[v]);
+    }
+    if constexpr (NF == 2) {
+      alpha_cell[0] = sh[lds_index<DIR, D>(R::ALPHA, a + 2, b)];
+      alpha_cell[1] = sh[lds_index<DIR, D>(R::ALPHA + 1, a + 2, b)];
+    }
+  }
+  __syncthreads();
+  if (centre_ok) {
+#pragma unroll
+    for (int v = 0; v < NEQ; ++v) sh[lds_index<DIR, D>(v, a, b)] = WLc[v];
+  }
+  __syncthreads();
+
+  // ---- (c) HLLC at the face c-1/2 between centres c-1 (left) and c (right) ----
+  Real F[NEQ];
+  Real uf = Real(0);
+  const bool face_ok = centre_ok && a >= 1;
+  if (face_ok) {
+    Real WL[NEQ];
+#pragma unroll
+    for (int v = 0; v < NEQ; ++v) WL[v] = sh[lds_index<DIR, D>(v, a - 1, b)];
+    const bool bad = hllc<NF, D, DIR, Real>(pm, WL, WRc, F, uf);
+    if (bad) atomicOr(flag, 1);
+  }
+  __syncthreads();
+  if (face_ok) {
+#pragma unroll
+    for (int v = 0; v < NEQ; ++v) sh[lds_index<DIR, D>(v, a, b)] = F[v];
+    sh[lds_index<DIR, D>(NEQ, a, b)] = uf;
+  }
+  __syncthreads();
+
+  // ---- (d) axis contribution for output cell c --------------------------------
+  if (!(line_ok && a >= 1 && a <= TL::TA - 2 && c >= 0 && c < nd)) return;
+  if constexpr (DIR == 0) ox = c;
+  else if constexpr (DIR == 1) oy = c;
+  else oz = c;
+  const long long cell = ((long long)oz * ny + oy) * nx + ox;
+  const Real inv_dx = Real(pm.inv_dx[DIR]);
+  const Real uhi = sh[lds_index<DIR, D>(NEQ, a + 1, b)];
+  const Real div = inv_dx * (uhi - uf);
+#pragma unroll
+  for (int v = 0; v < NEQ; ++v) {
+    Real Dv = inv_dx * (F[v] - sh[lds_index<DIR, D>(v, a + 1, b)]);
+    if constexpr (NF == 2) {
+      if (v == R::ALPHA) Dv = Dv + alpha_cell[0] * div;
+      if (v == R::ALPHA + 1) Dv = Dv + alpha_cell[1] * div;
+    }
+    const long long e = v * nc + cell;
+    Real r = Dv;
+    if constexpr (MODE & MODE_ACC) r = acc[e] + Dv;
+    if constexpr (MODE & MODE_STEP) {
+      // SSP-RK3, Shu-Osher form (Sec. 3.4), combined in double
+      const double dt = st.dt_ptr ? *st.dt_ptr : st.dt;
+      const double qs = double(qk[e]) + dt * double(r);
+      double out;
+      if (st.stage == 1)
+        out = qs;
+      else if (st.stage == 2)
+        out = 0.75 * double(qn[e]) + 0.25 * qs;
+      else
+        out = (1.0 / 3.0) * double(qn[e]) + (2.0 / 3.0) * qs;
+      qout[e] = Real(out);
+    } else {
+      acc[e] = r;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// host launchers
+// ---------------------------------------------------------------------------
+template <int NF, int D, int DIR, typename Real, int MODE>
+static hipError_t launch_one(const Params& pm, const Real* qk, Real* acc, const Real* qn, Real* qout,
+                             StageArgs st, int* flag, hipStream_t s, PassTimer* tm) {
+  using TL = Tile<DIR, D>;
+  dim3 block, grid;
+  const int nx = pm.n[0], ny = pm.n[1], nz = pm.n[2];
+  if constexpr (DIR == 0) {
+    block = dim3(TL::TA, TL::TB, 1);
+    grid = dim3((nx + TL::OUT - 1) / TL::OUT, (ny + TL::TB - 1) / TL::TB, nz);
+  } else if constexpr (DIR == 1) {
+    block = dim3(TL::TB, TL::TA, 1);
+    grid = dim3((nx + TL::TB - 1) / TL::TB, (ny + TL::OUT - 1) / TL::OUT, nz);
+  } else {
+    block = dim3(TL::TB, TL::TA, 1);
+    grid = dim3((nx + TL::TB - 1) / TL::TB, ny, (nz + TL::OUT - 1) / TL::OUT);
+  }
+  if (tm) tm->begin(KIND_PASS_X + DIR, s);
+  hipLaunchKernelGGL((sweep_kernel<NF, D, DIR, Real, MODE>), grid, block, 0, s, pm, qk, acc, qn, qout, st,
+                     flag);
+  if (tm) tm->end(KIND_PASS_X + DIR, s);
+  return hipGetLastError();
+}
+
+// All axes of one RHS evaluation.  final_step: the last axis combines into qout.
+template <int NF, int D, typename Real>
+static hipError_t launch_rhs_t(const Params& pm, const Real* qk, Real* acc, const Real* qn, Real* qout,
+                               StageArgs st, bool final_step, int* flag, hipStream_t s, PassTimer* tm) {
+  hipError_t e = hipSuccess;
+  if constexpr (D == 1) {
+    if (final_step)
+      e = launch_one<NF, D, 0, Real, MODE_STEP>(pm, qk, acc, qn, qout, st, flag, s, tm);
+    else
+      e = launch_one<NF, D, 0, Real, MODE_WRITE>(pm, qk, acc, qn, qout, st, flag, s, tm);
+  } else {
+    e = launch_one<NF, D, 0, Real, MODE_WRITE>(pm, qk, acc, qn, qout, st, flag, s, tm);
+    if (e != hipSuccess) return e;
+    if constexpr (D == 3) {
+      e = launch_one<NF, D, 1, Real, MODE_ACC>(pm, qk, acc, qn, qout, st, flag, s, tm);
+      if (e != hipSuccess) return e;
+    }
+    constexpr int LAST = D - 1;
+    if (final_step)
+      e = launch_one<NF, D, LAST, Real, MODE_ACC | MODE_STEP>(pm, qk, acc, qn, qout, st, flag, s, tm);
+    else
+      e = launch_one<NF, D, LAST, Real, MODE_ACC>(pm, qk, acc, qn, qout, st, flag, s, tm);
+  }
+  return e;
+}
+
+template <typename Real>
+hipError_t launch_rhs(int nf, int ndim, const Params& pm, const Real* qk, Real* acc, const Real* qn,
+                      Real* qout, StageArgs st, bool final_step, int* flag, hipStream_t s, PassTimer* tm) {
+#define MFC_CASE(NF, D)                                                                        \
+  if (nf == NF && ndim == D)                                                                   \
+    return launch_rhs_t<NF, D, Real>(pm, qk, acc, qn, qout, st, final_step, flag, s, tm);
+  MFC_CASE(1, 1)
+  MFC_CASE(1, 2)
+  MFC_CASE(1, 3)
+  MFC_CASE(2, 1)
+  MFC_CASE(2, 2)
+  MFC_CASE(2, 3)
+#undef MFC_CASE
+  return hipErrorInvalidValue;
+}
+
+template hipError_t launch_rhs<double>(int, int, const Params&, const double*, double*, const double*,
+                                       double*, StageArgs, bool, int*, hipStream_t, PassTimer*);
+template hipError_t launch_rhs<float>(int, int, const Params&, const float*, float*, const float*, float*,
+                                      StageArgs, bool, int*, hipStream_t, PassTimer*);
+
+}  // namespace mfc

@@ -1,0 +1,384 @@
+// vjp.hip -- discrete adjoint (vector-Jacobian product) of the RHS, of the
+// SSP-RK3 step and of the field conversions.
+//
+// For rhs = L(q) and a cotangent rbar, mfc_rhs_vjp forms qbar = (dL/dq)^T rbar
+// axis by axis, in three deterministic passes (no atomics):
+//   face pass   one thread per face f (low side of cell f, f = 0..n): reload the
+//               six-cell stencil (ghost remap), recompute primitives, WENO and
+//               HLLC, form the face cotangents Fbar = (rbar_f - rbar_{f-1})/dx and
+//               ufbar = sum_j (alpha_j rbar_alpha_j)_{f-1} - (...)_f (times 1/dx),
+//               then HLLC^T and WENO^T give the primitive cotangents of the six
+//               stencil positions, stored per face;
+//   gather pass one thread per position p = -3..n+2 (interior and ghost): sums the
+//               contributions of the six faces whose stencils hold p, applies
+//               cons->prim^T at the state of p, adds the direct alpha term
+//               rbar_alpha (u_{+1/2} - u_{-1/2})/dx, and writes interior
+//               cotangents to qbar, ghost cotangents to a boundary buffer;
+//   boundary    one thread per line: adds the ghost cotangents to the interior
+//               cells they were copied from (mirror sign for slip walls).
+#include "adjoint.h"
+#include "internal.h"
+
+namespace mfc {
+
+struct AxisGeom {
+  int fx, fy, fz;   // extent of the enumerated grid
+  long long count;  // fx*fy*fz
+};
+
+template <int DIR>
+__device__ __forceinline__ int line_of(int i, int j, int k, int nx, int ny) {
+  if constexpr (DIR == 0) return k * ny + j;
+  else if constexpr (DIR == 1) return k * nx + i;
+  else return j * nx + i;
+}
+
+template <int NF, int D, int DIR>
+__global__ __launch_bounds__(128) void vjp_face_kernel(Params pm, const double* __restrict__ q,
+                                                       const double* __restrict__ rbar, double* __restrict__ G,
+                                                       double* __restrict__ UF, AxisGeom fg) {
+  using R = Rows<NF, D>;
+  constexpr int NEQ = R::NEQ;
+  const long long id = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (id >= fg.count) return;
+  const int nx = pm.n[0], ny = pm.n[1];
+  const int nd = pm.n[DIR];
+  const long long nc = pm.ncell;
+  const int i = (int)(id % fg.fx);
+  const int j = (int)((id / fg.fx) % fg.fy);
+  const int k = (int)(id / ((long long)fg.fx * fg.fy));
+  int idx[3] = {i, j, k};
+  const int f = idx[DIR];
+
+  double Wc[6][NEQ];
+  double rb[2][NEQ];
+#pragma unroll
+  for (int s = 0; s < 6; ++s) {
+    bool flip;
+    const int g = ghost_index(f - 3 + s, nd, pm.bc_lo[DIR], pm.bc_hi[DIR], flip);
+    int id2[3] = {i, j, k};
+    id2[DIR] = g;
+    const long long cell = ((long long)id2[2] * ny + id2[1]) * nx + id2[0];
+    double U[NEQ];
+#pragma unroll
+    for (int v = 0; v < NEQ; ++v) U[v] = q[v * nc + cell];
+    if (flip) U[R::MOM + DIR] = -U[R::MOM + DIR];
+    cons_to_prim<NF, D>(pm, U, Wc[s]);
+    if (s == 2 || s == 3) {
+      const int c = f - 3 + s;  // cells f-1 and f
+      const bool inside = c >= 0 && c < nd;
+#pragma unroll
+      for (int v = 0; v < NEQ; ++v) rb[s - 2][v] = inside ? rbar[v * nc + cell] : 0.0;
+    }
+  }
+  double WL[NEQ], WR[NEQ];
+#pragma unroll
+  for (int v = 0; v < NEQ; ++v) {
+    double l, r, t;
+    weno5_js(Wc[0][v], Wc[1][v], Wc[2][v], Wc[3][v], Wc[4][v], pm.eps, l, t);
+    weno5_js(Wc[1][v], Wc[2][v], Wc[3][v], Wc[4][v], Wc[5][v], pm.eps, t, r);
+    WL[v] = l;
+    WR[v] = r;
+  }
+  double F[NEQ], uf;
+  (void)hllc<NF, D, DIR, double>(pm, WL, WR, F, uf);
+
+  const double inv_dx = pm.inv_dx[DIR];
+  double Fb[NEQ];
+#pragma unroll
+  for (int v = 0; v < NEQ; ++v) Fb[v] = inv_dx * (rb[1][v] - rb[0][v]);
+  double ufb = 0.0;
+  if constexpr (NF == 2) {
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+      ufb += Wc[2][R::ALPHA + a] * rb[0][R::ALPHA + a] - Wc[3][R::ALPHA + a] * rb[1][R::ALPHA + a];
+    ufb *= inv_dx;
+  }
+  double WLb[NEQ], WRb[NEQ];
+#pragma unroll
+  for (int v = 0; v < NEQ; ++v) WLb[v] = WRb[v] = 0.0;
+  hllc_vjp<NF, D, DIR>(pm, WL, WR, Fb, ufb, WLb, WRb);
+
+  const long long nf = fg.count;
+#pragma unroll
+  for (int v = 0; v < NEQ; ++v) {
+    double g[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    weno_left_vjp(Wc[0][v], Wc[1][v], Wc[2][v], Wc[3][v], Wc[4][v], pm.eps, WLb[v], g);
+    double gr[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    weno_left_vjp(Wc[5][v], Wc[4][v], Wc[3][v], Wc[2][v], Wc[1][v], pm.eps, WRb[v], gr);
+    g[1] += gr[4];
+    g[2] += gr[3];
+    g[3] += gr[2];
+    g[4] += gr[1];
+    g[5] += gr[0];
+#pragma unroll
+    for (int s = 0; s < 6; ++s) G[(long long)(s * NEQ + v) * nf + id] = g[s];
+  }
+  UF[id] = uf;
+}
+
+template <int NF, int D, int DIR>
+__global__ __launch_bounds__(256) void vjp_gather_kernel(Params pm, const double* __restrict__ q,
+                                                         const double* __restrict__ rbar,
+                                                         const double* __restrict__ G,
+                                                         const double* __restrict__ UF, double* __restrict__ qbar,
+                                                         double* __restrict__ BB, AxisGeom eg, AxisGeom fg,
+                                                         int accumulate) {
+  using R = Rows<NF, D>;
+  constexpr int NEQ = R::NEQ;
+  const long long id = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (id >= eg.count) return;
+  const int nx = pm.n[0], ny = pm.n[1];
+  const int nd = pm.n[DIR];
+  const long long nc = pm.ncell;
+  int idx[3] = {(int)(id % eg.fx), (int)((id / eg.fx) % eg.fy), (int)(id / ((long long)eg.fx * eg.fy))};
+  const int p = idx[DIR] - 3;  // position along DIR, -3 .. nd+2
+  // faces holding p in their stencils: f = p + 3 - s, s = 0..5
+  double wb[NEQ];
+#pragma unroll
+  for (int v = 0; v < NEQ; ++v) wb[v] = 0.0;
+  const long long nfc = fg.count;
+#pragma unroll
+  for (int s = 0; s < 6; ++s) {
+    const int f = p + 3 - s;
+    if (f < 0 || f > nd) continue;
+    int fi[3] = {idx[0], idx[1], idx[2]};
+    fi[DIR] = f;
+    const long long fid = ((long long)fi[2] * fg.fy + fi[1]) * fg.fx + fi[0];
+#pragma unroll
+    for (int v = 0; v < NEQ; ++v) wb[v] += G[(long long)(s * NEQ + v) * nfc + fid];
+  }
+  bool flip;
+  const int g = ghost_index(p, nd, pm.bc_lo[DIR], pm.bc_hi[DIR], flip);
+  int ci[3] = {idx[0], idx[1], idx[2]};
+  ci[DIR] = g;
+  const long long cell = ((long long)ci[2] * ny + ci[1]) * nx + ci[0];
+  double U[NEQ], Ub[NEQ];
+#pragma unroll
+  for (int v = 0; v < NEQ; ++v) {
+    U[v] = q[v * nc + cell];
+    Ub[v] = 0.0;
+  }
+  if (flip) U[R::MOM + DIR] = -U[R::MOM + DIR];
+  cons_to_prim_vjp<NF, D>(pm, U, wb, Ub);
+  if (p >= 0 && p < nd) {
+    if constexpr (NF == 2) {
+      int f0[3] = {idx[0], idx[1], idx[2]};
+      f0[DIR] = p;
+      const long long fid0 = ((long long)f0[2] * fg.fy + f0[1]) * fg.fx + f0[0];
+      int f1[3] = {idx[0], idx[1], idx[2]};
+      f1[DIR] = p + 1;
+      const long long fid1 = ((long long)f1[2] * fg.fy + f1[1]) * fg.fx + f1[0];
+      const double div = pm.inv_dx[DIR] * (UF[fid1] - UF[fid0]);
+#pragma unroll
+      for (int a = 0; a < 2; ++a) Ub[R::ALPHA + a] += rbar[(R::ALPHA + a) * nc + cell] * div;
+    }
+#pragma unroll
+    for (int v = 0; v < NEQ; ++v) {
+      const long long e = v * nc + cell;
+      qbar[e] = accumulate ? qbar[e] + Ub[v] : Ub[v];
+    }
+  } else {
+    if (flip) Ub[R::MOM + DIR] = -Ub[R::MOM + DIR];
+    const int side = p < 0 ? 0 : 1;
+    const int layer = p < 0 ? -1 - p : p - nd;
+    const long long nlines = nc / nd;
+    const int line = line_of<DIR>(idx[0], idx[1], idx[2], nx, ny);
+#pragma unroll
+    for (int v = 0; v < NEQ; ++v) BB[((long long)((side * 3 + layer) * NEQ + v)) * nlines + line] = Ub[v];
+  }
+}
+
+template <int NF, int D, int DIR>
+__global__ __launch_bounds__(256) void vjp_boundary_kernel(Params pm, const double* __restrict__ BB,
+                                                           double* __restrict__ qbar) {
+  using R = Rows<NF, D>;
+  constexpr int NEQ = R::NEQ;
+  const int nx = pm.n[0], ny = pm.n[1], nz = pm.n[2];
+  const int nd = pm.n[DIR];
+  const long long nc = pm.ncell;
+  const long long nlines = nc / nd;
+  const long long line = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (line >= nlines) return;
+  int a0, a1;  // the two fixed coordinates of the line
+  if constexpr (DIR == 0) {
+    a0 = (int)(line % ny);
+    a1 = (int)(line / ny);
+  } else if constexpr (DIR == 1) {
+    a0 = (int)(line % nx);
+    a1 = (int)(line / nx);
+  } else {
+    a0 = (int)(line % nx);
+    a1 = (int)(line / nx);
+  }
+  (void)nz;
+  for (int side = 0; side < 2; ++side) {
+    for (int layer = 0; layer < 3; ++layer) {
+      const int p = side == 0 ? -1 - layer : nd + layer;
+      bool flip;
+      const int g = ghost_index(p, nd, pm.bc_lo[DIR], pm.bc_hi[DIR], flip);
+      long long cell;
+      if constexpr (DIR == 0) cell = ((long long)a1 * ny + a0) * nx + g;
+      else if constexpr (DIR == 1) cell = ((long long)a1 * ny + g) * nx + a0;
+      else cell = ((long long)g * ny + a1) * nx + a0;
+#pragma unroll
+      for (int v = 0; v < NEQ; ++v) {
+        const long long e = v * nc + cell;
+        qbar[e] += BB[((long long)((side * 3 + layer) * NEQ + v)) * nlines + line];
+      }
+    }
+  }
+}
+
+template <int NF, int D, int DIR>
+static hipError_t launch_axis_vjp(const Params& pm, const double* q, const double* rbar, double* qbar,
+                                  const VjpScratch& sc, bool accumulate, hipStream_t s) {
+  AxisGeom fg{pm.n[0] + (DIR == 0), pm.n[1] + (DIR == 1), pm.n[2] + (DIR == 2), 0};
+  fg.count = (long long)fg.fx * fg.fy * fg.fz;
+  AxisGeom eg{pm.n[0] + 6 * (DIR == 0), pm.n[1] + 6 * (DIR == 1), pm.n[2] + 6 * (DIR == 2), 0};
+  eg.count = (long long)eg.fx * eg.fy * eg.fz;
+  hipLaunchKernelGGL((vjp_face_kernel<NF, D, DIR>), dim3((unsigned)((fg.count + 127) / 128)), dim3(128), 0, s, pm, q,
+                     rbar, sc.G, sc.UF, fg);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((vjp_gather_kernel<NF, D, DIR>), dim3((unsigned)((eg.count + 255) / 256)), dim3(256), 0, s, pm,
+                     q, rbar, sc.G, sc.UF, qbar, sc.BB + (size_t)DIR * sc.bb_stride, eg, fg, accumulate ? 1 : 0);
+  return hipGetLastError();
+}
+
+template <int NF, int D, int DIR>
+static hipError_t launch_axis_boundary(const Params& pm, double* qbar, const VjpScratch& sc, hipStream_t s) {
+  const long long nlines = pm.ncell / pm.n[DIR];
+  hipLaunchKernelGGL((vjp_boundary_kernel<NF, D, DIR>), dim3((unsigned)((nlines + 255) / 256)), dim3(256), 0, s, pm,
+                     sc.BB + (size_t)DIR * sc.bb_stride, qbar);
+  return hipGetLastError();
+}
+
+template <int NF, int D>
+static hipError_t launch_rhs_vjp_t(const Params& pm, const double* q, const double* rbar, double* qbar,
+                                   const VjpScratch& sc, bool accumulate, hipStream_t s, PassTimer* tm) {
+  hipError_t e;
+  if (tm) tm->begin(KIND_VJP, s);
+  e = launch_axis_vjp<NF, D, 0>(pm, q, rbar, qbar, sc, accumulate, s);
+  if (e == hipSuccess && D > 1) e = launch_axis_vjp<NF, D, (D > 1 ? 1 : 0)>(pm, q, rbar, qbar, sc, true, s);
+  if (e == hipSuccess && D > 2) e = launch_axis_vjp<NF, D, (D > 2 ? 2 : 0)>(pm, q, rbar, qbar, sc, true, s);
+  if (e == hipSuccess) e = launch_axis_boundary<NF, D, 0>(pm, qbar, sc, s);
+  if (e == hipSuccess && D > 1) e = launch_axis_boundary<NF, D, (D > 1 ? 1 : 0)>(pm, qbar, sc, s);
+  if (e == hipSuccess && D > 2) e = launch_axis_boundary<NF, D, (D > 2 ? 2 : 0)>(pm, qbar, sc, s);
+  if (tm) tm->end(KIND_VJP, s);
+  return e;
+}
+
+hipError_t launch_rhs_vjp(int nf, int ndim, const Params& pm, const double* q, const double* rbar, double* qbar,
+                          const VjpScratch& sc, bool accumulate, hipStream_t s, PassTimer* tm) {
+#define MFC_CASE(NF, D) \
+  if (nf == NF && ndim == D) return launch_rhs_vjp_t<NF, D>(pm, q, rbar, qbar, sc, accumulate, s, tm);
+  MFC_CASE(1, 1)
+  MFC_CASE(1, 2)
+  MFC_CASE(1, 3)
+  MFC_CASE(2, 1)
+  MFC_CASE(2, 2)
+  MFC_CASE(2, 3)
+#undef MFC_CASE
+  return hipErrorInvalidValue;
+}
+
+// ---------------------------------------------------------------------------
+// per-cell conversions' adjoints
+// ---------------------------------------------------------------------------
+template <int NF, int D, bool TO_CONS>
+__global__ __launch_bounds__(256) void convert_vjp_kernel(Params pm, const double* __restrict__ x,
+                                                          const double* __restrict__ ybar, double* __restrict__ xbar,
+                                                          int accumulate) {
+  using R = Rows<NF, D>;
+  constexpr int NEQ = R::NEQ;
+  const long long nc = pm.ncell;
+  for (long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x; c < nc; c += (long long)gridDim.x * blockDim.x) {
+    double X[NEQ], Yb[NEQ], Xb[NEQ];
+#pragma unroll
+    for (int v = 0; v < NEQ; ++v) {
+      X[v] = x[v * nc + c];
+      Yb[v] = ybar[v * nc + c];
+      Xb[v] = 0.0;
+    }
+    if constexpr (TO_CONS)
+      prim_to_cons_vjp<NF, D>(pm, X, Yb, Xb);
+    else
+      cons_to_prim_vjp<NF, D>(pm, X, Yb, Xb);
+#pragma unroll
+    for (int v = 0; v < NEQ; ++v) {
+      const long long e = v * nc + c;
+      xbar[e] = accumulate ? xbar[e] + Xb[v] : Xb[v];
+    }
+  }
+}
+
+hipError_t launch_convert_vjp(int nf, int ndim, bool to_cons, const Params& pm, const double* x, const double* ybar,
+                              double* xbar, bool accumulate, hipStream_t s) {
+  long long nb = (pm.ncell + 255) / 256;
+  if (nb > 65536) nb = 65536;
+  dim3 grid((unsigned)nb), block(256);
+  const int acc = accumulate ? 1 : 0;
+#define MFC_CASE(NF, D)                                                                                       \
+  if (nf == NF && ndim == D) {                                                                                \
+    if (to_cons)                                                                                              \
+      hipLaunchKernelGGL((convert_vjp_kernel<NF, D, true>), grid, block, 0, s, pm, x, ybar, xbar, acc);       \
+    else                                                                                                      \
+      hipLaunchKernelGGL((convert_vjp_kernel<NF, D, false>), grid, block, 0, s, pm, x, ybar, xbar, acc);      \
+    return hipGetLastError();                                                                                 \
+  }
+  MFC_CASE(1, 1)
+  MFC_CASE(1, 2)
+  MFC_CASE(1, 3)
+  MFC_CASE(2, 1)
+  MFC_CASE(2, 2)
+  MFC_CASE(2, 3)
+#undef MFC_CASE
+  return hipErrorInvalidValue;
+}
+
+// ---------------------------------------------------------------------------
+// reverse SSP-RK3 combinations (Shu-Osher form)
+//   qbar2 = 2/3 (qbar3 + dt v3),  qbarn  = 1/3 qbar3          (v3 = L^T(q2) qbar3)
+//   qbar1 = 1/4 (qbar2 + dt v2),  qbarn += 3/4 qbar2          (v2 = L^T(q1) qbar2)
+//   qbarn += qbar1 + dt v1                                    (v1 = L^T(qn) qbar1)
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void adj_stage3_kernel(long long n, double dt, const double* __restrict__ a,
+                                                         const double* __restrict__ v, double* __restrict__ b2,
+                                                         double* __restrict__ qnb) {
+  for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (long long)gridDim.x * blockDim.x) {
+    const double x = a[e];
+    b2[e] = (2.0 / 3.0) * (x + dt * v[e]);
+    qnb[e] = (1.0 / 3.0) * x;
+  }
+}
+__global__ __launch_bounds__(256) void adj_stage2_kernel(long long n, double dt, const double* __restrict__ b2,
+                                                         const double* __restrict__ v, double* __restrict__ b1,
+                                                         double* __restrict__ qnb) {
+  for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (long long)gridDim.x * blockDim.x) {
+    const double x = b2[e];
+    b1[e] = 0.25 * (x + dt * v[e]);
+    qnb[e] = qnb[e] + 0.75 * x;
+  }
+}
+__global__ __launch_bounds__(256) void adj_stage1_kernel(long long n, double dt, const double* __restrict__ b1,
+                                                         const double* __restrict__ v, double* __restrict__ qnb) {
+  for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (long long)gridDim.x * blockDim.x)
+    qnb[e] = qnb[e] + (b1[e] + dt * v[e]);
+}
+
+hipError_t launch_adj_stage(int which, long long n, double dt, const double* x, const double* v, double* out,
+                            double* qnb, hipStream_t s) {
+  long long nb = (n + 255) / 256;
+  if (nb > 65536) nb = 65536;
+  dim3 grid((unsigned)nb), block(256);
+  if (which == 3)
+    hipLaunchKernelGGL(adj_stage3_kernel, grid, block, 0, s, n, dt, x, v, out, qnb);
+  else if (which == 2)
+    hipLaunchKernelGGL(adj_stage2_kernel, grid, block, 0, s, n, dt, x, v, out, qnb);
+  else
+    hipLaunchKernelGGL(adj_stage1_kernel, grid, block, 0, s, n, dt, x, v, qnb);
+  return hipGetLastError();
+}
+
+}  // namespace mfc

@@ -1,0 +1,154 @@
+"""Python front end of libmfc355: one context per problem, torch device tensors.
+
+Every method marshals arguments to one C-ABI call of the same name; the
+computation runs in the library's HIP kernels on the current torch stream.
+"""
+from __future__ import annotations
+
+import ctypes
+
+import torch
+
+from . import _lib as L
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Solver:
+    """Owns one mfc_ctx.  `precision` is "fp64" or "fp32" (the mixed FP32 form)."""
+
+    def __init__(self, ndim, n, num_fluids, dx, gamma, pi_inf, bc_lo, bc_hi, weno_eps=1e-6,
+                 precision="fp64", device="cuda"):
+        self.lib = L.load()
+        self.precision = precision
+        prec = L.MFC_FP64 if precision == "fp64" else L.MFC_FP32_MIXED
+        self.prob = L.make_problem(ndim, n, num_fluids, dx, gamma, pi_inf, bc_lo, bc_hi, weno_eps, prec)
+        self.dtype = torch.float64 if precision == "fp64" else torch.float32
+        self.device = torch.device(device)
+        rc = self.lib.mfc_validate(ctypes.byref(self.prob))
+        if rc != L.MFC_OK:
+            raise L.MfcError(rc, "invalid problem")
+        self.neq = self.lib.mfc_num_eqs(ctypes.byref(self.prob))
+        self.n = tuple(self.prob.n)
+        self.shape = (self.neq, self.n[2], self.n[1], self.n[0])
+        self.ndim = ndim
+        self.num_fluids = num_fluids
+        self.dx = tuple(self.prob.dx)
+        with torch.cuda.device(self.device):
+            h = ctypes.c_void_p()
+            rc = self.lib.mfc_create(ctypes.byref(self.prob), ctypes.byref(h))
+        if rc != L.MFC_OK:
+            raise L.MfcError(rc, "mfc_create")
+        self.ctx = h
+        self._scal = torch.zeros(4, dtype=torch.float64, device=self.device)
+
+    @classmethod
+    def from_case(cls, case, precision="fp64", device="cuda"):
+        return cls(**case.problem_kwargs(), precision=precision, device=device)
+
+    def __del__(self):
+        ctx = getattr(self, "ctx", None)
+        if ctx is not None and ctx.value:
+            try:
+                self.lib.mfc_destroy(ctx)
+            except Exception:
+                pass
+            self.ctx = None
+
+    # -------------------------------------------------------------- helpers
+    def _check(self, rc, what):
+        if rc != L.MFC_OK:
+            msg = self.lib.mfc_last_error(self.ctx).decode()
+            raise L.MfcError(rc, f"{what}: {msg}")
+
+    def _arr(self, t, name="q"):
+        if not isinstance(t, torch.Tensor):
+            raise TypeError(f"{name} must be a torch tensor")
+        if t.dtype != self.dtype or t.device.type != "cuda" or tuple(t.shape) != self.shape or not t.is_contiguous():
+            raise ValueError(f"{name}: expected contiguous {self.dtype} cuda tensor of shape {self.shape}, "
+                             f"got {t.dtype} {t.device} {tuple(t.shape)}")
+        return t
+
+    def empty(self):
+        return torch.empty(self.shape, dtype=self.dtype, device=self.device)
+
+    def to_device(self, a):
+        return torch.as_tensor(a).to(device=self.device, dtype=self.dtype).contiguous()
+
+    # -------------------------------------------------------------- entry points
+    def prim_to_cons(self, w, out=None):
+        w = self._arr(w, "w")
+        q = self.empty() if out is None else self._arr(out, "out")
+        self._check(self.lib.mfc_prim_to_cons(self.ctx, _ptr(w), _ptr(q), _stream()), "mfc_prim_to_cons")
+        return q
+
+    def cons_to_prim(self, q, out=None):
+        q = self._arr(q)
+        w = self.empty() if out is None else self._arr(out, "out")
+        self._check(self.lib.mfc_cons_to_prim(self.ctx, _ptr(q), _ptr(w), _stream()), "mfc_cons_to_prim")
+        return w
+
+    def rhs(self, q, out=None):
+        q = self._arr(q)
+        r = self.empty() if out is None else self._arr(out, "out")
+        self._check(self.lib.mfc_rhs(self.ctx, _ptr(q), _ptr(r), _stream()), "mfc_rhs")
+        return r
+
+    def max_signal(self, q):
+        """Device scalar tensor holding max_cells sum_d (|u_d| + c)/dx_d."""
+        q = self._arr(q)
+        out = torch.empty(1, dtype=torch.float64, device=self.device)
+        self._check(self.lib.mfc_max_signal(self.ctx, _ptr(q), _ptr(out), _stream()), "mfc_max_signal")
+        return out
+
+    def step(self, q, cfl=0.0, dt_fixed=0.0, t_remaining=0.0, dt_out=None):
+        """Advance q in place by one SSP-RK3 step.  dt_out: optional device double tensor."""
+        q = self._arr(q)
+        dp = ctypes.c_void_p(dt_out.data_ptr()) if dt_out is not None else ctypes.c_void_p()
+        self._check(self.lib.mfc_step(self.ctx, _ptr(q), float(cfl), float(dt_fixed), float(t_remaining), dp,
+                                      _stream()), "mfc_step")
+        return q
+
+    def conserved_sums(self, q):
+        q = self._arr(q)
+        out = torch.empty(self.neq, dtype=torch.float64, device=self.device)
+        self._check(self.lib.mfc_conserved_sums(self.ctx, _ptr(q), _ptr(out), _stream()), "mfc_conserved_sums")
+        return out
+
+    def check(self):
+        """Synchronize and raise MfcError(MFC_ERR_NONFINITE) if a bad state was met."""
+        self._check(self.lib.mfc_check(self.ctx, _stream()), "mfc_check")
+
+    def set_timing(self, enable=True):
+        self._check(self.lib.mfc_set_timing(self.ctx, int(bool(enable))), "mfc_set_timing")
+
+    def get_timing(self):
+        """{kind: (ms_sum, count)} for kinds signal, x, y, z, vjp since the last call."""
+        import numpy as np
+        ms = np.zeros(5, dtype=np.float64)
+        cnt = np.zeros(5, dtype=np.int64)
+        self._check(self.lib.mfc_get_timing(self.ctx, ms.ctypes.data_as(ctypes.c_void_p),
+                                            cnt.ctypes.data_as(ctypes.c_void_p)), "mfc_get_timing")
+        names = ["signal", "pass_x", "pass_y", "pass_z", "vjp"]
+        return {k: (float(ms[i]), int(cnt[i])) for i, k in enumerate(names)}
+
+    def run(self, q, nsteps, cfl=0.0, dt_fixed=0.0):
+        for _ in range(nsteps):
+            self.step(q, cfl=cfl, dt_fixed=dt_fixed)
+        return q
+
+    def run_to(self, q, t_end, cfl):
+        """Advance to t_end with CFL steps clipped at t_end (reads dt back each step)."""
+        dt = torch.zeros(1, dtype=torch.float64, device=self.device)
+        t, k = 0.0, 0
+        while t < t_end:
+            self.step(q, cfl=cfl, t_remaining=t_end - t, dt_out=dt)
+            t += float(dt.item())
+            k += 1
+        return k

@@ -1,0 +1,219 @@
+"""HIP path (through the C ABI) against the CPU FP64 oracle on the same seeded inputs.
+
+Bar: per conservative field, max|gpu - oracle| / max|oracle| <= 1e-12 (FP64).
+Sizes span several tiles with ragged tails on every axis; full-size
+configurations are checked on sampled cells or after a full step.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import workloads as W
+from helpers import field_errors
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-12
+
+
+def _solver(case, precision="fp64"):
+    from paper_2503_07953_amd.solver import Solver
+    return Solver.from_case(case, precision=precision)
+
+
+def _say(*a):
+    print("[gpu-parity]", *a, flush=True)
+
+
+CASES = [
+    # (ndim, n, nf, bc)
+    (1, (200,), 1, (W.EXTRAP,)),
+    (1, (131,), 2, (W.SLIPWALL,)),
+    (1, (64,), 2, (W.PERIODIC,)),
+    (2, (150, 70), 2, (W.EXTRAP, W.SLIPWALL)),
+    (2, (64, 93), 1, (W.PERIODIC, W.EXTRAP)),
+    (2, (37, 41), 2, (W.PERIODIC, W.PERIODIC)),
+    (3, (70, 33, 29), 2, (W.SLIPWALL, W.EXTRAP, W.PERIODIC)),
+    (3, (40, 40, 40), 1, (W.EXTRAP, W.PERIODIC, W.SLIPWALL)),
+    (3, (3, 3, 3), 2, (W.EXTRAP, W.SLIPWALL, W.PERIODIC)),
+]
+
+
+@pytest.mark.parametrize("nd,n,nf,bc", CASES)
+def test_rhs_matches_oracle(nd, n, nf, bc):
+    _say("rhs", nd, n, nf, bc)
+    c = W.random_case(nd, n, nf=nf, seed=100 + nd, bc=bc, speed=400.0 if nf == 1 else 200.0)
+    O = oracle.Oracle(c)
+    q = O.prim_to_cons(c.w)
+    ref = O.rhs(q)
+    S = _solver(c)
+    qd = S.to_device(q)
+    got = S.rhs(qd).cpu().numpy()
+    S.check()
+    err = field_errors(got, ref)
+    assert err.max() <= TOL, err
+
+
+@pytest.mark.parametrize("nd,n,nf,bc", CASES[:7])
+def test_prim_cons_and_signal_match_oracle(nd, n, nf, bc):
+    c = W.random_case(nd, n, nf=nf, seed=200 + nd, bc=bc)
+    O = oracle.Oracle(c)
+    S = _solver(c)
+    q_ref = O.prim_to_cons(c.w)
+    q = S.prim_to_cons(S.to_device(c.w)).cpu().numpy()
+    assert field_errors(q, q_ref).max() <= 4e-16
+    w = S.cons_to_prim(S.to_device(q_ref)).cpu().numpy()
+    w_ref = O.cons_to_prim(q_ref)
+    assert field_errors(w, w_ref).max() <= 1e-13
+    s = S.max_signal(S.to_device(q_ref)).item()
+    assert abs(s / O.max_signal(q_ref) - 1) <= 1e-14
+    sums = S.conserved_sums(S.to_device(q_ref)).cpu().numpy()
+    sums_ref = O.conserved_sums(q_ref)
+    scale = np.abs(q_ref).sum(axis=(1, 2, 3)) * np.prod([c.dx[d] for d in range(nd)])
+    assert np.all(np.abs(sums - sums_ref) <= 1e-13 * scale)
+
+
+@pytest.mark.parametrize("nd,n,nf,bc,nsteps", [
+    (2, (96, 80), 2, (W.EXTRAP, W.SLIPWALL), 20),
+    (3, (40, 36, 30), 2, (W.PERIODIC, W.EXTRAP, W.SLIPWALL), 5),
+    (1, (300,), 1, (W.EXTRAP,), 50),
+])
+def test_cfl_steps_match_oracle(nd, n, nf, bc, nsteps):
+    _say("steps", nd, n, nf, bc, nsteps)
+    c = W.random_case(nd, n, nf=nf, seed=300 + nd, bc=bc, speed=150.0)
+    O = oracle.Oracle(c)
+    q = O.prim_to_cons(c.w)
+    S = _solver(c)
+    qd = S.to_device(q)
+    dts = O.run(q, nsteps, cfl=0.5)
+    dt = torch.zeros(1, dtype=torch.float64, device="cuda")
+    gdts = []
+    for _ in range(nsteps):
+        S.step(qd, cfl=0.5, dt_out=dt)
+        gdts.append(dt.item())
+    S.check()
+    assert np.allclose(gdts, dts, rtol=1e-13, atol=0)
+    err = field_errors(qd.cpu().numpy(), q)
+    assert err.max() <= TOL, err
+
+
+def test_sod_full_run_matches_oracle_and_exact():
+    from oracle import exact_riemann as er
+    c = W.sod(200)
+    O = oracle.Oracle(c)
+    q = O.prim_to_cons(c.w)
+    n_or = O.run_to(q, 0.2, 0.5)
+    S = _solver(c)
+    qd = S.prim_to_cons(S.to_device(c.w))
+    n_gpu = S.run_to(qd, 0.2, 0.5)
+    S.check()
+    assert n_gpu == n_or
+    got = qd.cpu().numpy()
+    assert field_errors(got, q).max() <= TOL
+    w = S.cons_to_prim(qd).cpu().numpy()[:, 0, 0]
+    x = (np.arange(200) + 0.5) / 200
+    r, u, p = er.sample((1, 0, 1), (0.125, 0, 0.1), (x - 0.5) / 0.2)
+    assert np.mean(np.abs(w[0] - r)) <= 4e-3
+
+
+def test_uniform_state_gives_zero_rhs_bitwise():
+    n = (70, 20, 18)
+    w = np.zeros((8,) + n[::-1])
+    w[0], w[1], w[2], w[3], w[4], w[5], w[6], w[7] = 300.0, 0.7, 12.0, -5.0, 3.0, 2e5, 0.3, 0.7
+    c = W.Case("u", 3, n, 2, (0.1, 0.1, 0.1), (6.12, 1.4), (3.43e8, 0.0), (0,) * 3, (0,) * 3, w)
+    S = _solver(c)
+    r = S.rhs(S.prim_to_cons(S.to_device(w))).cpu().numpy()
+    assert np.all(r == 0.0)
+
+
+def test_periodic_shift_and_determinism_bitwise():
+    c = W.random_case(2, (100, 60), nf=2, seed=7, bc=(W.PERIODIC, W.PERIODIC))
+    S = _solver(c)
+    q = S.prim_to_cons(S.to_device(c.w))
+    r1 = S.rhs(q).cpu().numpy()
+    r2 = S.rhs(q).cpu().numpy()
+    assert np.array_equal(r1, r2)
+    qs = torch.roll(q, shifts=(7, -5), dims=(3, 2)).contiguous()
+    rs = S.rhs(qs).cpu().numpy()
+    assert np.array_equal(rs, np.roll(r1, (7, -5), axis=(3, 2)))
+    a = q.clone()
+    b = q.clone()
+    S.run(a, 3, cfl=0.5)
+    S.run(b, 3, cfl=0.5)
+    assert torch.equal(a, b)
+
+
+def test_nonfinite_state_is_reported():
+    from paper_2503_07953_amd import _lib as L
+    c = W.random_case(1, (64,), nf=1, seed=1)
+    O = oracle.Oracle(c)
+    q = O.prim_to_cons(c.w)
+    q[2, 0, 0, 20] = -1e6  # energy below kinetic: negative pressure
+    S = _solver(c)
+    S.rhs(S.to_device(q))
+    with pytest.raises(L.MfcError) as e:
+        S.check()
+    assert e.value.code == L.MFC_ERR_NONFINITE
+    S.check()  # flag is cleared
+
+
+def test_invalid_arguments_rejected():
+    from paper_2503_07953_amd import _lib as L
+    c = W.random_case(2, (16, 16), nf=2, seed=1)
+    S = _solver(c)
+    q = S.prim_to_cons(S.to_device(c.w))
+    with pytest.raises(L.MfcError) as e:
+        S.step(q, cfl=0.5, dt_fixed=1e-7)
+    assert e.value.code == L.MFC_ERR_ARG
+    with pytest.raises(L.MfcError) as e:
+        S.step(q)
+    assert e.value.code == L.MFC_ERR_ARG
+    import ctypes
+    rc = S.lib.mfc_rhs(S.ctx, ctypes.c_void_p(q.data_ptr() + 4), ctypes.c_void_p(q.data_ptr() + 8), None)
+    assert rc == L.MFC_ERR_ARG
+
+
+# --------------------------------------------------------------------------
+# configurations at their full sizes
+# --------------------------------------------------------------------------
+@pytest.mark.timeout(900)
+@pytest.mark.slow
+def test_shock_cylinder_512_full_run_matches_oracle():
+    """The 2D shock-cylinder configuration, 512^2, 500 CFL steps."""
+    c = W.shock_cylinder(512)
+    O = oracle.Oracle(c)
+    q = O.prim_to_cons(c.w)
+    S = _solver(c)
+    qd = S.to_device(q)
+    _say("C1 gpu run")
+    S.run(qd, c.steps, cfl=0.5)
+    S.check()
+    _say("C1 oracle run")
+    O.run(q, c.steps, cfl=0.5)
+    err = field_errors(qd.cpu().numpy(), q)
+    _say("C1 errors", err)
+    assert err.max() <= TOL, err
+
+
+@pytest.mark.timeout(600)
+@pytest.mark.slow
+def test_bubble_cloud_256_full_size_step_and_sampled_rhs():
+    """The 3D bubble cloud at 256^3: sampled RHS cells, then one full CFL step."""
+    c = W.bubble_cloud(256)
+    O = oracle.Oracle(c)
+    q = O.prim_to_cons(c.w)
+    S = _solver(c)
+    qd = S.to_device(q)
+    r = S.rhs(qd).cpu().numpy().reshape(c.neq, -1)
+    rng = np.random.default_rng(0)
+    cells = rng.choice(c.ncell, size=4000, replace=False)
+    ref = O.rhs_cells(q, cells).T
+    err = field_errors(r[:, cells], ref)
+    assert err.max() <= TOL, err
+    _say("C2 step")
+    S.step(qd, cfl=0.5)
+    S.check()
+    O.step(q, cfl=0.5)
+    err = field_errors(qd.cpu().numpy(), q)
+    _say("C2 step errors", err)
+    assert err.max() <= TOL, err
