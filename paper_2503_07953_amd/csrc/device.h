@@ -251,10 +251,12 @@ __host__ __device__ __forceinline__ bool hllc(const Params& pm, const T* WL, con
     F[R::ALPHA] = W[R::ALPHA] * uf;
     F[R::ALPHA + 1] = W[R::ALPHA + 1] * uf;
   }
-  T chk = uf - uf;
+  // explicit class checks: an "x - x == 0" test would not survive fused
+  // multiply-add contraction (a*b - a*b becomes the rounding residual)
+  bool finite = isfinite(uf);
 #pragma unroll
-  for (int v = 0; v < R::NEQ; ++v) chk += F[v] - F[v];
-  return !(c2L > 0.0 && c2R > 0.0 && chk == T(0));
+  for (int v = 0; v < R::NEQ; ++v) finite = finite && isfinite(F[v]);
+  return !(c2L > 0.0 && c2R > 0.0 && finite);
 }
 
 }  // namespace mfc

@@ -121,6 +121,48 @@ class Solver:
         self._check(self.lib.mfc_conserved_sums(self.ctx, _ptr(q), _ptr(out), _stream()), "mfc_conserved_sums")
         return out
 
+    # -------------------------------------------------------------- adjoint
+    def _out(self, out, accumulate):
+        if out is None:
+            if accumulate:
+                raise ValueError("accumulate needs an output tensor")
+            return self.empty()
+        return self._arr(out, "out")
+
+    def rhs_vjp(self, q, rhs_bar, out=None, accumulate=False):
+        """(dL/dq)^T rhs_bar at q."""
+        q = self._arr(q)
+        rb = self._arr(rhs_bar, "rhs_bar")
+        o = self._out(out, accumulate)
+        self._check(self.lib.mfc_rhs_vjp(self.ctx, _ptr(q), _ptr(rb), _ptr(o), int(accumulate), _stream()),
+                    "mfc_rhs_vjp")
+        return o
+
+    def step_vjp(self, q_n, dt, qnp1_bar, out=None):
+        """(dq^{n+1}/dq^n)^T qnp1_bar for a fixed-dt step from q_n."""
+        q = self._arr(q_n, "q_n")
+        b = self._arr(qnp1_bar, "qnp1_bar")
+        o = self._out(out, False)
+        self._check(self.lib.mfc_step_vjp(self.ctx, _ptr(q), float(dt), _ptr(b), _ptr(o), _stream()),
+                    "mfc_step_vjp")
+        return o
+
+    def cons_to_prim_vjp(self, q, w_bar, out=None, accumulate=False):
+        q = self._arr(q)
+        wb = self._arr(w_bar, "w_bar")
+        o = self._out(out, accumulate)
+        self._check(self.lib.mfc_cons_to_prim_vjp(self.ctx, _ptr(q), _ptr(wb), _ptr(o), int(accumulate),
+                                                  _stream()), "mfc_cons_to_prim_vjp")
+        return o
+
+    def prim_to_cons_vjp(self, w, q_bar, out=None, accumulate=False):
+        w = self._arr(w, "w")
+        qb = self._arr(q_bar, "q_bar")
+        o = self._out(out, accumulate)
+        self._check(self.lib.mfc_prim_to_cons_vjp(self.ctx, _ptr(w), _ptr(qb), _ptr(o), int(accumulate),
+                                                  _stream()), "mfc_prim_to_cons_vjp")
+        return o
+
     def check(self):
         """Synchronize and raise MfcError(MFC_ERR_NONFINITE) if a bad state was met."""
         self._check(self.lib.mfc_check(self.ctx, _stream()), "mfc_check")

@@ -1,0 +1,212 @@
+"""Hand-written HIP adjoint against torch autograd of the FP64 torch reference.
+
+The reference (oracle/torch_ref.py) reproduces the C oracle bit for bit and
+its autograd gradient is pinned against finite differences of the C oracle
+(tests/test_oracle_pins.py), so it fixes the discrete gradient that the HIP
+adjoint must reproduce element by element.
+
+Tolerance.  WENO-JS weight derivatives scale like 1/(eps + beta) and react to
+rounding-level data: perturbing q by one ulp moves the reference adjoint by
+1e-10 .. 1e-8 (relative, per row).  No float64 implementation can agree with
+the reference better than that spread, so each test measures it (helpers.
+noise_floor) and requires the HIP adjoint to lie within 10x of it (and never
+needs more than 1e-7); a wrong or missing term shows as 1e-3 .. 1.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import workloads as W
+from helpers import field_errors, noise_floor
+from oracle import torch_ref as TR
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-11
+
+
+def _say(*a):
+    print("[gpu-adjoint]", *a, flush=True)
+
+
+def _solver(case):
+    from paper_2503_07953_amd.solver import Solver
+    return Solver.from_case(case, precision="fp64")
+
+
+CASES = [
+    (1, (70,), 2, (W.SLIPWALL,)),
+    (1, (64,), 1, (W.EXTRAP,)),
+    (2, (70, 45), 2, (W.EXTRAP, W.SLIPWALL)),
+    (2, (33, 40), 2, (W.PERIODIC, W.EXTRAP)),
+    (2, (40, 36), 1, (W.PERIODIC, W.PERIODIC)),
+    (3, (20, 17, 14), 2, (W.SLIPWALL, W.PERIODIC, W.EXTRAP)),
+    (3, (3, 4, 5), 2, (W.EXTRAP, W.SLIPWALL, W.PERIODIC)),
+]
+
+
+@pytest.mark.parametrize("nd,n,nf,bc", CASES)
+def test_rhs_vjp_matches_reference_autograd(nd, n, nf, bc):
+    _say("rhs_vjp", nd, n, nf, bc)
+    c = W.random_case(nd, n, nf=nf, seed=40 + nd, bc=bc, speed=300.0 if nf == 1 else 150.0)
+    O = oracle.Oracle(c)
+    q = O.prim_to_cons(c.w)
+    P = TR.Problem.from_case(c)
+    rng = np.random.default_rng(1)
+    lam = rng.normal(size=q.shape)
+    def fn(x):
+        xt = torch.from_numpy(x.copy()).requires_grad_(True)
+        return torch.autograd.grad(TR.rhs(P, xt), xt, torch.from_numpy(lam))[0].numpy()
+
+    ref, spread = noise_floor(fn, q)
+    S = _solver(c)
+    got = S.rhs_vjp(S.to_device(q), S.to_device(lam)).cpu().numpy()
+    err = field_errors(got, ref)
+    _say("errors", err, "floor", spread)
+    tol = np.minimum(np.maximum(10 * spread, TOL), 1e-7)
+    assert np.all(err <= tol), (err, spread)
+    # accumulate mode adds onto the output
+    base = S.to_device(np.ones_like(q))
+    S.rhs_vjp(S.to_device(q), S.to_device(lam), out=base, accumulate=True)
+    err2 = field_errors(base.cpu().numpy() - 1.0, ref)
+    assert np.all(err2 <= np.maximum(tol, 1e-9))
+
+
+@pytest.mark.parametrize("nd,n,nf,bc", CASES[:6])
+def test_step_vjp_matches_reference_autograd(nd, n, nf, bc):
+    _say("step_vjp", nd, n, nf, bc)
+    c = W.random_case(nd, n, nf=nf, seed=50 + nd, bc=bc, speed=150.0)
+    O = oracle.Oracle(c)
+    q = O.prim_to_cons(c.w)
+    dt = 0.4 / O.max_signal(q)
+    P = TR.Problem.from_case(c)
+    lam = np.random.default_rng(2).normal(size=q.shape)
+    def fn(x):
+        xt = torch.from_numpy(x.copy()).requires_grad_(True)
+        return torch.autograd.grad(TR.step(P, xt, dt), xt, torch.from_numpy(lam))[0].numpy()
+
+    ref, spread = noise_floor(fn, q)
+    S = _solver(c)
+    got = S.step_vjp(S.to_device(q), dt, S.to_device(lam)).cpu().numpy()
+    err = field_errors(got, ref)
+    _say("errors", err, "floor", spread)
+    tol = np.minimum(np.maximum(10 * spread, TOL), 1e-7)
+    assert np.all(err <= tol), (err, spread)
+
+
+@pytest.mark.parametrize("nd,n,nf", [(2, (30, 20), 2), (3, (8, 7, 6), 2), (1, (40,), 1)])
+def test_conversion_vjps_match_reference(nd, n, nf):
+    c = W.random_case(nd, n, nf=nf, seed=7)
+    P = TR.Problem.from_case(c)
+    S = _solver(c)
+    rng = np.random.default_rng(3)
+    qb = rng.normal(size=c.w.shape)
+
+    def fw(x):
+        xt = torch.from_numpy(x.copy()).requires_grad_(True)
+        return torch.autograd.grad(TR.prim_to_cons(P, xt), xt, torch.from_numpy(qb))[0].numpy()
+
+    ref, spread = noise_floor(fw, c.w)
+    got = S.prim_to_cons_vjp(S.to_device(c.w), S.to_device(qb)).cpu().numpy()
+    assert np.all(field_errors(got, ref) <= np.maximum(10 * spread, 1e-14))
+    q = TR.prim_to_cons(P, torch.from_numpy(c.w)).numpy()
+    qt = torch.from_numpy(q.copy()).requires_grad_(True)
+    wb = rng.normal(size=c.w.shape)
+
+    def fn(x):
+        xt = torch.from_numpy(x.copy()).requires_grad_(True)
+        return torch.autograd.grad(TR.cons_to_prim(P, xt), xt, torch.from_numpy(wb))[0].numpy()
+
+    ref2, spread = noise_floor(fn, q)
+    got = S.cons_to_prim_vjp(S.to_device(q), S.to_device(wb)).cpu().numpy()
+    assert np.all(field_errors(got, ref2) <= np.maximum(10 * spread, 1e-14))
+
+
+def test_rhs_vjp_dot_product_against_gpu_forward_differences():
+    """<L(q+hv) - L(q-hv), lam>/2h (GPU forward) equals <v, L^T lam> (GPU adjoint)."""
+    c = W.random_case(2, (48, 40), nf=2, seed=11, bc=(W.EXTRAP, W.SLIPWALL), speed=50.0,
+                      pressure_jump=1.0, interface=False)
+    S = _solver(c)
+    q = S.prim_to_cons(S.to_device(c.w))
+    rng = np.random.default_rng(0)
+    for _ in range(2):
+        v = torch.from_numpy(np.stack([W._smooth_field(rng, q.shape[1:], 2) for _ in range(q.shape[0])])).cuda()
+        v = v * q.abs()
+        lam = torch.from_numpy(rng.normal(size=q.shape)).cuda()
+        lhs = float((S.rhs_vjp(q, lam) * v).sum())
+        est = []
+        for h in (4e-9, 2e-9):
+            fd = (S.rhs((q + h * v).contiguous()) - S.rhs((q - h * v).contiguous())) / (2 * h)
+            est.append(float((fd * lam).sum()))
+        rich = (4 * est[1] - est[0]) / 3
+        assert abs(rich / lhs - 1) <= 1e-5, (lhs, est)
+
+
+def test_autograd_functions_chain():
+    from paper_2503_07953_amd import autograd as AG
+    c = W.random_case(2, (24, 20), nf=2, seed=3, bc=(W.EXTRAP, W.EXTRAP))
+    S = _solver(c)
+    P = TR.Problem.from_case(c)
+    w = torch.from_numpy(c.w.copy())
+    wd = S.to_device(c.w).requires_grad_(True)
+    dt = 2e-7
+    q = AG.PrimToCons.apply(wd, S)
+    q = AG.Step.apply(q, S, dt)
+    r = AG.RHS.apply(q, S)
+    loss = (r * r).sum() * 1e-20 + AG.ConsToPrim.apply(q, S)[4].sum()
+    loss.backward()
+    wt = w.clone().requires_grad_(True)
+    qt = TR.step(P, TR.prim_to_cons(P, wt), dt)
+    rt = TR.rhs(P, qt)
+    lt = (rt * rt).sum() * 1e-20 + TR.cons_to_prim(P, qt)[4].sum()
+    lt.backward()
+    assert field_errors(wd.grad.cpu().numpy(), wt.grad.numpy()).max() <= 1e-10
+
+
+@pytest.mark.timeout(600)
+@pytest.mark.slow
+def test_rollout_gradient_matches_reference_at_64():
+    """Adjoint problem at 64^2: gradient of the time-integrated wall pressure with
+    respect to the initial alpha_1 and p, HIP adjoint vs torch autograd (200 steps,
+    frozen dt, checkpoints every 20 steps)."""
+    from paper_2503_07953_amd import autograd as AG
+    c = W.adjoint_case(64, steps=200)
+    S = _solver(c)
+    O = oracle.Oracle(c)
+    dt = 0.5 / O.max_signal(O.prim_to_cons(c.w))
+    P = TR.Problem.from_case(c)
+    ex = c.extra
+
+    def ic(alpha1, p, lib):
+        rw = lib(ex["rho_water"])
+        ra = lib(ex["rho_air"])
+        u, v = lib(ex["u"]), lib(ex["v"])
+        rows = [alpha1 * rw, (1 - alpha1) * ra, u, v, p, alpha1, 1 - alpha1]
+        return torch.stack(rows).reshape(7, 1, 64, 64).contiguous()
+
+    a0 = c.w[5, 0].copy()
+    p0 = c.w[4, 0].copy()
+    # HIP adjoint
+    ag = torch.from_numpy(a0).cuda().requires_grad_(True)
+    pg = torch.from_numpy(p0).cuda().requires_grad_(True)
+    q0 = AG.PrimToCons.apply(ic(ag, pg, lambda a: torch.from_numpy(a).cuda()), S)
+    J = AG.rollout_objective(q0, S, c.steps, dt, every=20)
+    J.backward()
+    _say("J gpu", float(J))
+    # reference: torch autograd with per-step checkpointing
+    from torch.utils.checkpoint import checkpoint
+    at = torch.from_numpy(a0.copy()).requires_grad_(True)
+    pt = torch.from_numpy(p0.copy()).requires_grad_(True)
+    q = TR.prim_to_cons(P, ic(at, pt, torch.from_numpy))
+    Jt = torch.zeros((), dtype=torch.float64)
+    dy = c.dx[1]
+    for _ in range(c.steps):
+        q = checkpoint(lambda x: TR.step(P, x, dt), q, use_reentrant=False)
+        Jt = Jt + dt * dy * TR.cons_to_prim(P, q)[4, 0, :, 63].sum()
+    Jt.backward()
+    _say("J ref", float(Jt))
+    assert abs(float(J) / float(Jt) - 1) <= 1e-12
+    ga, gp = ag.grad.cpu().numpy(), pg.grad.cpu().numpy()
+    ra, rp = at.grad.numpy(), pt.grad.numpy()
+    assert np.abs(ga - ra).max() <= 1e-9 * np.abs(ra).max()
+    assert np.abs(gp - rp).max() <= 1e-9 * np.abs(rp).max()

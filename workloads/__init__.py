@@ -381,6 +381,13 @@ def random_case(ndim: int, n, nf: int = 2, seed: int = 0, bc=None, speed: float 
     nrm[ndim:] = 0
     nrm /= np.linalg.norm(nrm)
     plane = nrm[0] * (X - 0.5) + nrm[1] * (Y - 0.5) + nrm[2] * (Z - 0.5) - rng.uniform(-0.2, 0.2)
+    bc_tuple = _pad3(bc if bc is not None else (EXTRAP,) * 3, EXTRAP)
+    if any(bc_tuple[d] == PERIODIC for d in range(ndim)):
+        # a plane wrapped by a periodic axis leaves slots a few cells wide; use
+        # a ball that stays clear of the boundaries instead
+        cj = rng.uniform(0.4, 0.6, size=3)
+        cj[ndim:] = 0
+        plane = np.sqrt((X - cj[0]) ** 2 + (Y - cj[1]) ** 2 + (Z - cj[2]) ** 2) - 0.25
     jump = np.where(plane < 0, pressure_jump, 1.0)
     vel = [speed * _smooth_field(rng, shape, ndim) for _ in range(ndim)]
     if bc is None:
