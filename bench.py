@@ -88,6 +88,8 @@ def main():
     ap.add_argument("--n", type=int, default=256, help="bubble-cloud grid edge (256 = the configuration)")
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="also run a plain 1 GiB device-to-device copy (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -101,6 +103,14 @@ def main():
     from paper_2503_07953_amd.solver import Solver
 
     torch.cuda.set_device(0)
+    if args.calibrate_copy:
+        a = torch.ones(1 << 27, dtype=torch.float64, device="cuda")  # 1 GiB
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        log(f"copy calibration: 3 x {a.numel() * 8} bytes read and written")
+        del a, b
     t_ic = time.time()
     case = W.bubble_cloud(args.n)
     log(f"initial condition {case.name}: {time.time() - t_ic:.1f}s")
