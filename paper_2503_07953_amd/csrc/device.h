@@ -71,6 +71,22 @@ __host__ __device__ __forceinline__ void mixture(const Params& pm, T a0, T a1, T
   }
 }
 
+// Reciprocal of a positive normal double: hardware estimate (v_rcp_f64)
+// refined by two Newton steps (relative error a few ulp; no IEEE division
+// sequence).  The host compilation, used only to exercise this arithmetic on
+// the CPU, starts the same refinement from an exact quotient.
+__host__ __device__ __forceinline__ double fast_rcp(double x) {
+#ifdef __HIP_DEVICE_COMPILE__
+  double r = __builtin_amdgcn_rcp(x);
+#else
+  double r = 1.0 / x;
+#endif
+  double e = fma(-x, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-x, r, 1.0);
+  return fma(r, e, r);
+}
+
 // Conservative -> primitive for one cell, in double (the pressure inversion
 // from total energy stays in double in both precision forms):
 // u = (rho u)/rho, p = (rho E - rho |u|^2/2 - Pi)/Gamma.
@@ -79,7 +95,7 @@ __host__ __device__ __forceinline__ void cons_to_prim(const Params& pm, const do
   using R = Rows<NF, D>;
   double rho = U[0];
   if constexpr (NF == 2) rho = U[0] + U[1];
-  const double rinv = 1.0 / rho;
+  const double rinv = fast_rcp(rho);
   double usq = 0.0;
 #pragma unroll
   for (int d = 0; d < D; ++d) {
@@ -92,7 +108,7 @@ __host__ __device__ __forceinline__ void cons_to_prim(const Params& pm, const do
     mixture<NF, double>(pm, U[R::ALPHA], U[R::ALPHA + 1], Gam, Pi);
   else
     mixture<NF, double>(pm, 1.0, 0.0, Gam, Pi);
-  W[R::E] = (U[R::E] - 0.5 * rho * usq - Pi) / Gam;
+  W[R::E] = (U[R::E] - 0.5 * rho * usq - Pi) * fast_rcp(Gam);
 #pragma unroll
   for (int i = 0; i < NF; ++i) W[i] = U[i];
   if constexpr (NF == 2) {
@@ -104,7 +120,7 @@ __host__ __device__ __forceinline__ void cons_to_prim(const Params& pm, const do
 // Squared mixture sound speed, the mixture read as one stiffened gas with
 // gamma_m = 1 + 1/Gamma, pi_m = Pi/(Gamma + 1): c^2 = ((Gamma+1) p + Pi)/(Gamma rho).
 __host__ __device__ __forceinline__ double sound_speed_sq(double rho, double p, double Gam, double Pi) {
-  return ((Gam + 1.0) * p + Pi) / (Gam * rho);
+  return ((Gam + 1.0) * p + Pi) * fast_rcp(Gam * rho);
 }
 
 // ---------------------------------------------------------------------------
@@ -117,51 +133,66 @@ __host__ __device__ __forceinline__ double sound_speed_sq(double rho, double p, 
 __host__ __device__ __forceinline__ double sq(double x) { return x * x; }
 __host__ __device__ __forceinline__ float sq(float x) { return x * x; }
 
-// FP64: the normalized weights a_k/sum(a) with a_k = d_k/t_k, t_k =
-// (eps + beta_k)^2 are rewritten over the common denominator t0 t1 t2, so
-// a_k is proportional to d_k times the product of the other two t's; this
-// needs one division per biased value instead of four.  The products stay far
-// inside the double range (t <= ~1e40 for pressures of ~1e9 Pa).
+// FP64 WENO5-JS in difference form.  With D0..D3 the differences of the
+// five cell values (D_k = f_{k+1} - f_k), each candidate is the centre value
+// c plus a correction (e.g. q0 = c + (5 D1 - 2 D0)/6) and each smoothness
+// indicator is 13/12 u^2 + 1/4 v^2 with u, v two differences of differences;
+// here 4*beta = (13/3) u^2 + v^2 is formed and eps scaled by 4 to match, which
+// leaves the normalized weights unchanged.  The weights a_k = d_k/(eps +
+// beta_k)^2 are taken over the common denominator t0 t1 t2 (t_k = (eps +
+// beta_k)^2), so a_k is proportional to d_k times the product of the other two
+// t's; the two normalizations share one refined reciprocal.  The products stay
+// far inside the double range (t <= ~1e40 for pressure jumps of ~1e9 Pa).
 __host__ __device__ __forceinline__ void weno5_js(double a, double b, double c, double d, double e,
-                                         double eps, double& fl, double& fr) {
-  const double b0 = (13.0 / 12.0) * sq((a + c) - 2.0 * b) + 0.25 * sq((a + 3.0 * c) - 4.0 * b);
-  const double b1 = (13.0 / 12.0) * sq((b + d) - 2.0 * c) + 0.25 * sq(b - d);
-  const double b2 = (13.0 / 12.0) * sq((c + e) - 2.0 * d) + 0.25 * sq((3.0 * c + e) - 4.0 * d);
-  const double t0 = sq(eps + b0), t1 = sq(eps + b1), t2 = sq(eps + b2);
+                                                  double eps, double& fl, double& fr) {
+  const double D0 = b - a, D1 = c - b, D2 = d - c, D3 = e - d;
+  const double u0 = D1 - D0, v0 = 3.0 * D1 - D0;
+  const double u1 = D2 - D1, v1 = D1 + D2;
+  const double u2 = D3 - D2, v2 = D3 - 3.0 * D2;
+  const double e4 = 4.0 * eps;
+  const double s0 = e4 + ((13.0 / 3.0) * u0 * u0 + v0 * v0);
+  const double s1 = e4 + ((13.0 / 3.0) * u1 * u1 + v1 * v1);
+  const double s2 = e4 + ((13.0 / 3.0) * u2 * u2 + v2 * v2);
+  const double t0 = s0 * s0, t1 = s1 * s1, t2 = s2 * s2;
   const double p0 = t1 * t2, p1 = t0 * t2, p2 = t0 * t1;
-  // six times the candidate values
-  const double l0 = 2.0 * a - 7.0 * b + 11.0 * c;
-  const double l1 = -b + 5.0 * c + 2.0 * d;
-  const double l2 = 2.0 * c + 5.0 * d - e;
-  const double r0 = 2.0 * e - 7.0 * d + 11.0 * c;
-  const double r1 = -d + 5.0 * c + 2.0 * b;
-  const double r2 = 2.0 * c + 5.0 * b - a;
-  const double wl0 = 0.1 * p0, wl1 = 0.6 * p1, wl2 = 0.3 * p2;
-  const double wr0 = 0.1 * p2, wr1 = 0.6 * p1, wr2 = 0.3 * p0;
-  fl = (wl0 * l0 + wl1 * l1 + wl2 * l2) / (6.0 * (wl0 + wl1 + wl2));
-  fr = (wr0 * r0 + wr1 * r1 + wr2 * r2) / (6.0 * (wr0 + wr1 + wr2));
+  // six times the candidate corrections
+  const double l0 = 5.0 * D1 - 2.0 * D0, l1 = D1 + 2.0 * D2, l2 = 4.0 * D2 - D3;
+  const double r0 = 2.0 * D3 - 5.0 * D2, r1 = -(D2 + 2.0 * D1), r2 = D0 - 4.0 * D1;
+  const double w1 = 0.6 * p1;
+  const double wl0 = 0.1 * p0, wl2 = 0.3 * p2;
+  const double wr0 = 0.1 * p2, wr2 = 0.3 * p0;
+  const double nl = wl0 * l0 + w1 * l1 + wl2 * l2;
+  const double nr = wr0 * r0 + w1 * r1 + wr2 * r2;
+  const double dl = wl0 + w1 + wl2;
+  const double dr = wr0 + w1 + wr2;
+  const double inv = fast_rcp(6.0 * (dl * dr));
+  fl = c + nl * (dr * inv);
+  fr = c + nr * (dl * inv);
 }
 
-// FP32: products of t's would overflow float for pressure-sized data, so the
-// weights use hardware reciprocals of t_k (v_rcp_f32, ~1 ulp).
+// FP32: the same difference form; products of t's would overflow float for
+// pressure-sized data, so the weights use hardware reciprocals of t_k
+// (v_rcp_f32, ~1 ulp) and each biased value its own normalization.
 __device__ __forceinline__ void weno5_js(float a, float b, float c, float d, float e, float eps,
                                          float& fl, float& fr) {
-  const float b0 = (13.0f / 12.0f) * sq((a + c) - 2.0f * b) + 0.25f * sq((a + 3.0f * c) - 4.0f * b);
-  const float b1 = (13.0f / 12.0f) * sq((b + d) - 2.0f * c) + 0.25f * sq(b - d);
-  const float b2 = (13.0f / 12.0f) * sq((c + e) - 2.0f * d) + 0.25f * sq((3.0f * c + e) - 4.0f * d);
-  const float s0 = __builtin_amdgcn_rcpf(sq(eps + b0));
-  const float s1 = __builtin_amdgcn_rcpf(sq(eps + b1));
-  const float s2 = __builtin_amdgcn_rcpf(sq(eps + b2));
-  const float l0 = 2.0f * a - 7.0f * b + 11.0f * c;
-  const float l1 = -b + 5.0f * c + 2.0f * d;
-  const float l2 = 2.0f * c + 5.0f * d - e;
-  const float r0 = 2.0f * e - 7.0f * d + 11.0f * c;
-  const float r1 = -d + 5.0f * c + 2.0f * b;
-  const float r2 = 2.0f * c + 5.0f * b - a;
-  const float wl0 = 0.1f * s0, wl1 = 0.6f * s1, wl2 = 0.3f * s2;
-  const float wr0 = 0.1f * s2, wr1 = 0.6f * s1, wr2 = 0.3f * s0;
-  fl = (wl0 * l0 + wl1 * l1 + wl2 * l2) * __builtin_amdgcn_rcpf(6.0f * (wl0 + wl1 + wl2));
-  fr = (wr0 * r0 + wr1 * r1 + wr2 * r2) * __builtin_amdgcn_rcpf(6.0f * (wr0 + wr1 + wr2));
+  const float D0 = b - a, D1 = c - b, D2 = d - c, D3 = e - d;
+  const float u0 = D1 - D0, v0 = 3.0f * D1 - D0;
+  const float u1 = D2 - D1, v1 = D1 + D2;
+  const float u2 = D3 - D2, v2 = D3 - 3.0f * D2;
+  const float e4 = 4.0f * eps;
+  const float s0 = e4 + ((13.0f / 3.0f) * u0 * u0 + v0 * v0);
+  const float s1 = e4 + ((13.0f / 3.0f) * u1 * u1 + v1 * v1);
+  const float s2 = e4 + ((13.0f / 3.0f) * u2 * u2 + v2 * v2);
+  const float a0 = __builtin_amdgcn_rcpf(s0 * s0);
+  const float a1 = __builtin_amdgcn_rcpf(s1 * s1);
+  const float a2 = __builtin_amdgcn_rcpf(s2 * s2);
+  const float l0 = 5.0f * D1 - 2.0f * D0, l1 = D1 + 2.0f * D2, l2 = 4.0f * D2 - D3;
+  const float r0 = 2.0f * D3 - 5.0f * D2, r1 = -(D2 + 2.0f * D1), r2 = D0 - 4.0f * D1;
+  const float w1 = 0.6f * a1;
+  const float wl0 = 0.1f * a0, wl2 = 0.3f * a2;
+  const float wr0 = 0.1f * a2, wr2 = 0.3f * a0;
+  fl = c + (wl0 * l0 + w1 * l1 + wl2 * l2) * __builtin_amdgcn_rcpf(6.0f * (wl0 + w1 + wl2));
+  fr = c + (wr0 * r0 + w1 * r1 + wr2 * r2) * __builtin_amdgcn_rcpf(6.0f * (wr0 + w1 + wr2));
 }
 
 // ---------------------------------------------------------------------------
@@ -201,8 +232,9 @@ __host__ __device__ __forceinline__ bool hllc(const Params& pm, const T* WL, con
   const double SL = (sla <= slb) ? sla : slb;
   const double SR = (sra >= srb) ? sra : srb;
   const double drhoL = double(rhoL), drhoR = double(rhoR);
-  const double Sstar = (double(pR) - double(pL) + drhoL * dunL * (SL - dunL) - drhoR * dunR * (SR - dunR)) /
-                       (drhoL * (SL - dunL) - drhoR * (SR - dunR));
+  // the denominator is strictly negative for physical states (S_L < u_L, S_R > u_R)
+  const double Sstar = (double(pR) - double(pL) + drhoL * dunL * (SL - dunL) - drhoR * dunR * (SR - dunR)) *
+                       -fast_rcp(drhoR * (SR - dunR) - drhoL * (SL - dunL));
 
   // side the face takes and whether it lies in the star region
   const bool useL = (SL >= 0.0) || (Sstar >= 0.0);
@@ -227,7 +259,8 @@ __host__ __device__ __forceinline__ bool hllc(const Params& pm, const T* WL, con
   // values so that a degenerate S_K - u_K or S_K - S* cannot poison the flux
   const double dun = double(un);
   const double skmu = star ? (SK - dun) : 1.0;
-  const double chi = star ? skmu / (SK - Sstar) : 1.0;
+  const double chi = star ? skmu * fast_rcp(SK - Sstar) : 1.0;
+  const double p_over = double(p) * fast_rcp(skmu);
   const T s = star ? T(SK) : T(0);
   const T chiT = T(chi);
   const T SstarT = T(Sstar);
@@ -243,7 +276,7 @@ __host__ __device__ __forceinline__ bool hllc(const Params& pm, const T* WL, con
     F[R::MOM + e] = m * un + ((e == DIR) ? p : T(0)) + s * (us - m);
   }
   {
-    const T Es = chiT * (E + (SstarT - un) * (rho * SstarT + T(double(p) / skmu)));
+    const T Es = chiT * (E + (SstarT - un) * (rho * SstarT + T(p_over)));
     F[R::E] = (E + p) * un + s * (Es - E);
   }
   uf = star ? SstarT : un;
@@ -253,9 +286,9 @@ __host__ __device__ __forceinline__ bool hllc(const Params& pm, const T* WL, con
   }
   // explicit class checks: an "x - x == 0" test would not survive fused
   // multiply-add contraction (a*b - a*b becomes the rounding residual)
-  bool finite = isfinite(uf);
+  bool finite = __builtin_isfinite(uf);
 #pragma unroll
-  for (int v = 0; v < R::NEQ; ++v) finite = finite && isfinite(F[v]);
+  for (int v = 0; v < R::NEQ; ++v) finite = finite && __builtin_isfinite(F[v]);
   return !(c2L > 0.0 && c2R > 0.0 && finite);
 }
 

@@ -64,3 +64,26 @@ def noise_floor(fn, q, trials=3, seed=5):
         qp = q * (1.0 + rng.choice([-1.0, 0.0, 1.0], size=q.shape) * EPS)
         spread = np.maximum(spread, field_errors(fn(qp), base))
     return base, spread
+
+
+def rate_errors(a, b, q, smax, nf, ndim):
+    """RHS error per conservative field on the scale of the field's fastest rate.
+
+    A right-hand side is a difference of face fluxes; its rounding error is
+    relative to the fluxes, |F_v| <= |q_v| (|u| + c), not to the difference,
+    which is pure rounding noise wherever the exact RHS vanishes (fluid at rest
+    in uniform pressure).  Scale: max|q_v| * s_max with s_max = max over cells
+    of sum_d (|u_d| + c)/dx_d.  Momentum is one vector field.
+    """
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    q = np.asarray(q, dtype=np.float64)
+    out = []
+    for i in range(nf):
+        out.append(np.abs(a[i] - b[i]).max() / (np.abs(q[i]).max() * smax))
+    m = slice(nf, nf + ndim)
+    num = np.sqrt(((a[m] - b[m]) ** 2).sum(axis=0)).max()
+    out.append(num / (np.sqrt((q[m] ** 2).sum(axis=0)).max() * smax))
+    for r in range(nf + ndim, b.shape[0]):
+        out.append(np.abs(a[r] - b[r]).max() / (np.abs(q[r]).max() * smax))
+    return np.array(out)

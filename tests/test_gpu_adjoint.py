@@ -195,18 +195,34 @@ def test_rollout_gradient_matches_reference_at_64():
     _say("J gpu", float(J))
     # reference: torch autograd with per-step checkpointing
     from torch.utils.checkpoint import checkpoint
-    at = torch.from_numpy(a0.copy()).requires_grad_(True)
-    pt = torch.from_numpy(p0.copy()).requires_grad_(True)
-    q = TR.prim_to_cons(P, ic(at, pt, torch.from_numpy))
-    Jt = torch.zeros((), dtype=torch.float64)
-    dy = c.dx[1]
-    for _ in range(c.steps):
-        q = checkpoint(lambda x: TR.step(P, x, dt), q, use_reentrant=False)
-        Jt = Jt + dt * dy * TR.cons_to_prim(P, q)[4, 0, :, 63].sum()
-    Jt.backward()
-    _say("J ref", float(Jt))
-    assert abs(float(J) / float(Jt) - 1) <= 1e-12
+
+    def reference(a_init):
+        at = torch.from_numpy(a_init.copy()).requires_grad_(True)
+        pt = torch.from_numpy(p0.copy()).requires_grad_(True)
+        q = TR.prim_to_cons(P, ic(at, pt, torch.from_numpy))
+        Jt = torch.zeros((), dtype=torch.float64)
+        dy = c.dx[1]
+        for _ in range(c.steps):
+            q = checkpoint(lambda x: TR.step(P, x, dt), q, use_reentrant=False)
+            Jt = Jt + dt * dy * TR.cons_to_prim(P, q)[4, 0, :, 63].sum()
+        Jt.backward()
+        return float(Jt), at.grad.numpy(), pt.grad.numpy()
+
+    Jr, ra, rp = reference(a0)
+    _say("J ref", Jr)
+    # J sums wall pressures p = (E - ke - Pi)/Gamma; in water at 1 bar the
+    # cancellation amplifies state rounding by Pi/(Gamma p) ~ 2e4, so J agrees to
+    # ~1e-12 * 2e4 at most
+    assert abs(float(J) / Jr - 1) <= 1e-9
+    # gradient: within 10x the reference's own spread under a one-ulp change of alpha_1
+    rng = np.random.default_rng(9)
+    a1 = a0 * (1.0 + rng.choice([-1.0, 0.0, 1.0], size=a0.shape) * np.finfo(float).eps)
+    _, sa, sp = reference(a1)
+    fa = np.abs(sa - ra).max() / np.abs(ra).max()
+    fp = np.abs(sp - rp).max() / np.abs(rp).max()
     ga, gp = ag.grad.cpu().numpy(), pg.grad.cpu().numpy()
-    ra, rp = at.grad.numpy(), pt.grad.numpy()
-    assert np.abs(ga - ra).max() <= 1e-9 * np.abs(ra).max()
-    assert np.abs(gp - rp).max() <= 1e-9 * np.abs(rp).max()
+    ea = np.abs(ga - ra).max() / np.abs(ra).max()
+    ep = np.abs(gp - rp).max() / np.abs(rp).max()
+    _say("grad errors", ea, ep, "reference spread", fa, fp)
+    assert ea <= min(max(10 * fa, 1e-12), 1e-6)
+    assert ep <= min(max(10 * fp, 1e-12), 1e-6)

@@ -11,7 +11,7 @@ import torch
 
 import oracle
 import workloads as W
-from helpers import EPS, conservative_errors, field_errors
+from helpers import EPS, conservative_errors, field_errors, rate_errors
 
 pytestmark = pytest.mark.gpu
 TOL = 1e-12
@@ -225,7 +225,10 @@ def test_bubble_cloud_256_full_size_step_and_sampled_rhs():
     rng = np.random.default_rng(0)
     cells = rng.choice(c.ncell, size=4000, replace=False)
     ref = O.rhs_cells(q, cells).T
-    err = conservative_errors(r[:, cells], ref, 2, 3)
+    # bubbles at rest in uniform pressure: the exact alpha / air-density RHS is
+    # zero there, so errors are measured on the flux scale of each field
+    err = rate_errors(r[:, cells], ref, q.reshape(c.neq, -1)[:, cells], O.max_signal(q), 2, 3)
+    _say("C2 sampled rhs errors", err)
     assert err.max() <= TOL, err
     _say("C2 step")
     S.step(qd, cfl=0.5)
