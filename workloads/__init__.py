@@ -276,7 +276,7 @@ def _interface_height(n, seed_rng, amplitude):
     # separable evaluation: cos(2pi(kx x + ky y) + ph) = Re(e^{i ph} e^{2pi i kx x} e^{2pi i ky y})
     ex = np.exp(2j * np.pi * np.outer(kx, x))          # (m, nx)
     ey = np.exp(2j * np.pi * np.outer(ky, x))          # (m, ny)
-    eta = np.real(np.einsum("m,my,mx->yx", a * np.exp(1j * ph), ey, ex))
+    eta = np.real((ey.T * (a * np.exp(1j * ph))[None, :]) @ ex)
     return amplitude * eta / np.abs(eta).max()
 
 
