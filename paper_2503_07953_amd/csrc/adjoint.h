@@ -19,7 +19,7 @@ __host__ __device__ __forceinline__ void cons_to_prim_vjp(const Params& pm, cons
   using R = Rows<NF, D>;
   double rho = U[0];
   if constexpr (NF == 2) rho = U[0] + U[1];
-  const double rinv = 1.0 / rho;
+  const double rinv = fast_rcp(rho);
   double u[D];
   double usq = 0.0;
 #pragma unroll
@@ -32,9 +32,9 @@ __host__ __device__ __forceinline__ void cons_to_prim_vjp(const Params& pm, cons
     mixture<NF, double>(pm, U[R::ALPHA], U[R::ALPHA + 1], Gam, Pi);
   else
     mixture<NF, double>(pm, 1.0, 0.0, Gam, Pi);
-  const double p = (U[R::E] - 0.5 * rho * usq - Pi) / Gam;
+  const double gi = fast_rcp(Gam);
+  const double p = (U[R::E] - 0.5 * rho * usq - Pi) * gi;
   const double pb = wbar[R::E];
-  const double gi = 1.0 / Gam;
   Ubar[R::E] += pb * gi;
   const double keb = -pb * gi;   // d p / d ke
   const double Pib = -pb * gi;   // d p / d Pi
@@ -89,36 +89,56 @@ __host__ __device__ __forceinline__ void prim_to_cons_vjp(const Params& pm, cons
   }
 }
 
-// Adjoint of the left-biased WENO5-JS value at i+1/2 from f = (a, b, c, d, e):
-// y = sum_k a_k q_k / sum_k a_k, a_k = d_k/(eps + beta_k)^2.  Accumulates g[0..4].
+// Adjoint of the left-biased WENO5-JS value at i+1/2 from f = (a, b, c, d, e),
+// in the difference form of the forward: with D0..D3 the consecutive
+// differences, y = c + sum_k w_k l_k / 6, w_k = d_k s_k^-2 / sum_j d_j s_j^-2,
+// s_k = 4 (eps + beta_k) (a common factor the weights ignore), and
+// l_0 = 5D1 - 2D0, l_1 = D1 + 2D2, l_2 = 4D2 - D3 six times the candidate
+// corrections.  One refined reciprocal of N * s0 s1 s2 with
+// N = sum_k d_k prod_{j != k} s_j^2 gives both 1/N (the weights) and
+// 1/(s0 s1 s2) (the indicator derivatives dy/ds_k = -2 w_k (l_k/6 - (y - c))/s_k).
+// Accumulates g[0..4].
 __host__ __device__ __forceinline__ void weno_left_vjp(double a, double b, double c, double d, double e,
                                                        double eps, double gy, double* g) {
-  const double u0 = (a + c) - 2.0 * b, v0 = (a + 3.0 * c) - 4.0 * b;
-  const double u1 = (b + d) - 2.0 * c, v1 = b - d;
-  const double u2 = (c + e) - 2.0 * d, v2 = (3.0 * c + e) - 4.0 * d;
-  const double s0 = eps + ((13.0 / 12.0) * u0 * u0 + 0.25 * v0 * v0);
-  const double s1 = eps + ((13.0 / 12.0) * u1 * u1 + 0.25 * v1 * v1);
-  const double s2 = eps + ((13.0 / 12.0) * u2 * u2 + 0.25 * v2 * v2);
-  const double a0 = 0.1 / (s0 * s0), a1 = 0.6 / (s1 * s1), a2 = 0.3 / (s2 * s2);
-  const double S = a0 + a1 + a2;
-  const double Si = 1.0 / S;
-  const double q0 = (2.0 * a - 7.0 * b + 11.0 * c) / 6.0;
-  const double q1 = (-b + 5.0 * c + 2.0 * d) / 6.0;
-  const double q2 = (2.0 * c + 5.0 * d - e) / 6.0;
-  const double y = (a0 * q0 + a1 * q1 + a2 * q2) * Si;
-  // candidate values
-  const double q0b = gy * a0 * Si, q1b = gy * a1 * Si, q2b = gy * a2 * Si;
-  // weights -> smoothness indicators: d a_k / d beta_k = -2 a_k / s_k
-  const double b0b = gy * (q0 - y) * Si * (-2.0 * a0 / s0);
-  const double b1b = gy * (q1 - y) * Si * (-2.0 * a1 / s1);
-  const double b2b = gy * (q2 - y) * Si * (-2.0 * a2 / s2);
-  const double k = 13.0 / 6.0;
-  g[0] += b0b * (k * u0 + 0.5 * v0) + q0b * (2.0 / 6.0);
-  g[1] += b0b * (-2.0 * k * u0 - 2.0 * v0) + b1b * (k * u1 + 0.5 * v1) + q0b * (-7.0 / 6.0) - q1b * (1.0 / 6.0);
-  g[2] += b0b * (k * u0 + 1.5 * v0) + b1b * (-2.0 * k * u1) + b2b * (k * u2 + 1.5 * v2) + q0b * (11.0 / 6.0) +
-          q1b * (5.0 / 6.0) + q2b * (2.0 / 6.0);
-  g[3] += b1b * (k * u1 - 0.5 * v1) + b2b * (-2.0 * k * u2 - 2.0 * v2) + q1b * (2.0 / 6.0) + q2b * (5.0 / 6.0);
-  g[4] += b2b * (k * u2 + 0.5 * v2) - q2b * (1.0 / 6.0);
+  const double D0 = b - a, D1 = c - b, D2 = d - c, D3 = e - d;
+  const double u0 = D1 - D0, v0 = 3.0 * D1 - D0;
+  const double u1 = D2 - D1, v1 = D1 + D2;
+  const double u2 = D3 - D2, v2 = D3 - 3.0 * D2;
+  const double e4 = 4.0 * eps;
+  const double s0 = e4 + ((13.0 / 3.0) * u0 * u0 + v0 * v0);
+  const double s1 = e4 + ((13.0 / 3.0) * u1 * u1 + v1 * v1);
+  const double s2 = e4 + ((13.0 / 3.0) * u2 * u2 + v2 * v2);
+  const double m0 = s1 * s2, m1 = s0 * s2, m2 = s0 * s1;   // prod_{j != k} s_j
+  const double n0 = 0.1 * (m0 * m0), n1 = 0.6 * (m1 * m1), n2 = 0.3 * (m2 * m2);
+  const double N = n0 + n1 + n2;
+  const double P = s0 * m0;
+  const double inv = fast_rcp(N * P);
+  const double rN = P * inv;    // 1/N
+  const double rP = N * inv;    // 1/(s0 s1 s2)
+  const double w0 = n0 * rN, w1 = n1 * rN, w2 = n2 * rN;
+  const double l0 = 5.0 * D1 - 2.0 * D0, l1 = D1 + 2.0 * D2, l2 = 4.0 * D2 - D3;
+  const double k6 = 1.0 / 6.0;
+  const double dy = (w0 * l0 + w1 * l1 + w2 * l2) * k6;
+  // cotangents of l_k and s_k
+  const double gk = gy * k6;
+  const double gl0 = gk * w0, gl1 = gk * w1, gl2 = gk * w2;
+  const double g2 = -2.0 * gy * rP;
+  const double gs0 = g2 * w0 * (l0 * k6 - dy) * m0;
+  const double gs1 = g2 * w1 * (l1 * k6 - dy) * m1;
+  const double gs2 = g2 * w2 * (l2 * k6 - dy) * m2;
+  const double gu0 = gs0 * (26.0 / 3.0) * u0, gv0 = gs0 * 2.0 * v0;
+  const double gu1 = gs1 * (26.0 / 3.0) * u1, gv1 = gs1 * 2.0 * v1;
+  const double gu2 = gs2 * (26.0 / 3.0) * u2, gv2 = gs2 * 2.0 * v2;
+  // back to the differences, then to the five values
+  const double gD0 = -2.0 * gl0 - gu0 - gv0;
+  const double gD1 = 5.0 * gl0 + gl1 + gu0 + 3.0 * gv0 - gu1 + gv1;
+  const double gD2 = 2.0 * gl1 + 4.0 * gl2 + gu1 + gv1 - gu2 - 3.0 * gv2;
+  const double gD3 = -gl2 + gu2 + gv2;
+  g[0] -= gD0;
+  g[1] += gD0 - gD1;
+  g[2] += gy + gD1 - gD2;
+  g[3] += gD2 - gD3;
+  g[4] += gD3;
 }
 
 // Adjoint of one reconstruction centre: gL is the cotangent of the left-biased
@@ -175,10 +195,10 @@ __host__ __device__ __forceinline__ void side_scalars_vjp(const Params& pm, cons
   rhob += Eb * 0.5 * s.usq;
   // c = sqrt(c2), c2 = ((Gamma + 1) p + Pi)/(Gamma rho)
   if (cb != 0.0) {
-    const double c2b = cb / (2.0 * s.c);
-    const double den = s.Gam * s.rho;
-    const double Nb = c2b / den;
-    const double Db = -c2b * s.c2 / den;
+    const double c2b = 0.5 * cb * fast_rcp(s.c);
+    const double rden = fast_rcp(s.Gam * s.rho);
+    const double Nb = c2b * rden;
+    const double Db = -c2b * s.c2 * rden;
     Gamb += Nb * s.p + Db * s.rho;
     pb += Nb * (s.Gam + 1.0);
     Pib += Nb;
@@ -200,6 +220,7 @@ template <int NF, int D, int DIR>
 __host__ __device__ __forceinline__ void hllc_vjp(const Params& pm, const double* WL, const double* WR,
                                                   const double* Fb, double ufb, double* WLb, double* WRb) {
   using R = Rows<NF, D>;
+  constexpr int NEQ = R::NEQ;
   SideState<NF, D> L, Rs;
   side_state<NF, D, DIR>(pm, WL, L);
   side_state<NF, D, DIR>(pm, WR, Rs);
@@ -210,15 +231,25 @@ __host__ __device__ __forceinline__ void hllc_vjp(const Params& pm, const double
   const double SR = sr_left ? sra : srb;
   const double aL = SL - L.un, aR = SR - Rs.un;
   const double num = (Rs.p - L.p) + L.rho * L.un * aL - Rs.rho * Rs.un * aR;
-  const double den = L.rho * aL - Rs.rho * aR;
-  const double Sstar = num / den;
+  // S* = num / den with den = rho_L a_L - rho_R a_R < 0, formed as in the
+  // forward solver: num * -(1 / -den)
+  const double rnd = fast_rcp(Rs.rho * aR - L.rho * aL);
+  const double Sstar = num * -rnd;
   const bool useL = (SL >= 0.0) || (Sstar >= 0.0);
   const bool star = useL ? !(SL >= 0.0) : (SR > 0.0);
-  const double* W = useL ? WL : WR;
-  double* Wb = useL ? WLb : WRb;
-  const SideState<NF, D>& K = useL ? L : Rs;
+  // the side K the face takes, selected element by element (no pointer select)
+  double W[NEQ], Wk[NEQ];
+#pragma unroll
+  for (int v = 0; v < NEQ; ++v) {
+    W[v] = useL ? WL[v] : WR[v];
+    Wk[v] = 0.0;
+  }
+  const double Krho = useL ? L.rho : Rs.rho;
+  const double Kp = useL ? L.p : Rs.p;
+  const double Kun = useL ? L.un : Rs.un;
+  const double KE = useL ? L.E : Rs.E;
   const double SK = useL ? SL : SR;
-  const double uf = star ? Sstar : K.un;
+  const double uf = star ? Sstar : Kun;
 
   // side-K scalar cotangents
   double rhob = 0.0, Gamb = 0.0, Pib = 0.0, pb = 0.0, unb = 0.0, Eb = 0.0;
@@ -230,7 +261,7 @@ __host__ __device__ __forceinline__ void hllc_vjp(const Params& pm, const double
 #pragma unroll
     for (int j = 0; j < 2; ++j) {
       ufb_tot += Fb[R::ALPHA + j] * W[R::ALPHA + j];
-      Wb[R::ALPHA + j] += Fb[R::ALPHA + j] * uf;
+      Wk[R::ALPHA + j] += Fb[R::ALPHA + j] * uf;
     }
   }
   if (star)
@@ -243,65 +274,63 @@ __host__ __device__ __forceinline__ void hllc_vjp(const Params& pm, const double
     double unb_f = 0.0;
 #pragma unroll
     for (int i = 0; i < NF; ++i) {
-      Wb[i] += Fb[i] * K.un;
+      Wk[i] += Fb[i] * Kun;
       unb_f += Fb[i] * W[i];
     }
 #pragma unroll
     for (int e = 0; e < D; ++e) {
-      const double m = K.rho * W[R::MOM + e];
-      const double mb = Fb[R::MOM + e] * K.un;
+      const double m = Krho * W[R::MOM + e];
+      const double mb = Fb[R::MOM + e] * Kun;
       unb_f += Fb[R::MOM + e] * m;
       rhob += mb * W[R::MOM + e];
-      Wb[R::MOM + e] += mb * K.rho;
+      Wk[R::MOM + e] += mb * Krho;
     }
     pb += Fb[R::MOM + DIR];
-    unb_f += Fb[R::E] * (K.E + K.p);
-    Eb += Fb[R::E] * K.un;
-    pb += Fb[R::E] * K.un;
+    unb_f += Fb[R::E] * (KE + Kp);
+    Eb += Fb[R::E] * Kun;
+    pb += Fb[R::E] * Kun;
     unb += unb_f;
   }
 
   if (star) {
-    // F = F_K + S_K (U* - U)
-    const double A = SK - K.un;
+    // F = F_K + S_K (U* - U), U* = chi (U with u_DIR -> S*, E -> G)
+    const double A = SK - Kun;
     const double B = SK - Sstar;
-    const double chi = A / B;
-    const double h = K.rho * Sstar + K.p / A;
-    const double G = K.E + (Sstar - K.un) * h;
+    const double rA = fast_rcp(A), rB = fast_rcp(B);
+    const double chi = A * rB;
+    const double h = Krho * Sstar + Kp * rA;
+    const double G = KE + (Sstar - Kun) * h;
     double chib = 0.0;
-    // S_K (U* - U): cotangent of S_K, of U* and of U
 #pragma unroll
     for (int i = 0; i < NF; ++i) {
       const double Ui = W[i];
-      const double Us = chi * Ui;
-      SKb += Fb[i] * (Us - Ui);
+      SKb += Fb[i] * (chi * Ui - Ui);
       const double Usb = SK * Fb[i];
-      Wb[i] += -SK * Fb[i] + Usb * chi;
+      Wk[i] += -SK * Fb[i] + Usb * chi;
       chib += Usb * Ui;
     }
 #pragma unroll
     for (int e = 0; e < D; ++e) {
       const double ue = W[R::MOM + e];
-      const double m = K.rho * ue;
-      const double Us = (e == DIR) ? chi * K.rho * Sstar : chi * K.rho * ue;
+      const double m = Krho * ue;
+      const double Us = (e == DIR) ? chi * Krho * Sstar : chi * Krho * ue;
       SKb += Fb[R::MOM + e] * (Us - m);
       const double Usb = SK * Fb[R::MOM + e];
       const double mb = -SK * Fb[R::MOM + e];
       rhob += mb * ue;
-      Wb[R::MOM + e] += mb * K.rho;
+      Wk[R::MOM + e] += mb * Krho;
       if (e == DIR) {
-        chib += Usb * K.rho * Sstar;
+        chib += Usb * Krho * Sstar;
         rhob += Usb * chi * Sstar;
-        Sstarb += Usb * chi * K.rho;
+        Sstarb += Usb * chi * Krho;
       } else {
-        chib += Usb * K.rho * ue;
+        chib += Usb * Krho * ue;
         rhob += Usb * chi * ue;
-        Wb[R::MOM + e] += Usb * chi * K.rho;
+        Wk[R::MOM + e] += Usb * chi * Krho;
       }
     }
     {
-      const double Us = chi * G;
-      SKb += Fb[R::E] * (Us - K.E);
+      SKb += Fb[R::E] * (chi * G - KE);
       const double Usb = SK * Fb[R::E];
       Eb += -SK * Fb[R::E];
       chib += Usb * G;
@@ -309,14 +338,13 @@ __host__ __device__ __forceinline__ void hllc_vjp(const Params& pm, const double
       Eb += Gb;
       Sstarb += Gb * h;
       unb -= Gb * h;
-      const double hb = Gb * (Sstar - K.un);
+      const double hb = Gb * (Sstar - Kun);
       rhob += hb * Sstar;
-      Sstarb += hb * K.rho;
-      pb += hb / A;
-      double Ab = -hb * K.p / (A * A);
-      // chi = A / B
-      Ab += chib / B;
-      const double Bb = -chib * A / (B * B);
+      Sstarb += hb * Krho;
+      pb += hb * rA;
+      // h holds p / A; chi = A / B
+      const double Ab = -hb * Kp * (rA * rA) + chib * rB;
+      const double Bb = -chib * chi * rB;
       SKb += Ab + Bb;
       unb -= Ab;
       Sstarb -= Bb;
@@ -332,16 +360,16 @@ __host__ __device__ __forceinline__ void hllc_vjp(const Params& pm, const double
       SLb += SKb;
     else
       SRb += SKb;
-    const double numb = Sstarb / den;
-    const double denb = -Sstarb * Sstar / den;
+    const double numb = -Sstarb * rnd;          // Sstarb / den
+    const double denb = Sstarb * Sstar * rnd;   // -Sstarb S* / den
     pRb += numb;
     pLb -= numb;
     rhoLb += numb * L.un * aL + denb * aL;
     unLb += numb * L.rho * aL;
-    double aLb = numb * L.rho * L.un + denb * L.rho;
+    const double aLb = numb * L.rho * L.un + denb * L.rho;
     rhoRb -= numb * Rs.un * aR + denb * aR;
     unRb -= numb * Rs.rho * aR;
-    double aRb = -numb * Rs.rho * Rs.un - denb * Rs.rho;
+    const double aRb = -numb * Rs.rho * Rs.un - denb * Rs.rho;
     SLb += aLb;
     unLb -= aLb;
     SRb += aRb;
@@ -362,14 +390,16 @@ __host__ __device__ __forceinline__ void hllc_vjp(const Params& pm, const double
     }
   }
   // merge the selected side's own cotangents
-  if (useL) {
-    rhoLb += rhob;
-    unLb += unb;
-    pLb += pb;
-  } else {
-    rhoRb += rhob;
-    unRb += unb;
-    pRb += pb;
+  rhoLb += useL ? rhob : 0.0;
+  unLb += useL ? unb : 0.0;
+  pLb += useL ? pb : 0.0;
+  rhoRb += useL ? 0.0 : rhob;
+  unRb += useL ? 0.0 : unb;
+  pRb += useL ? 0.0 : pb;
+#pragma unroll
+  for (int v = 0; v < NEQ; ++v) {
+    WLb[v] += useL ? Wk[v] : 0.0;
+    WRb[v] += useL ? 0.0 : Wk[v];
   }
   side_scalars_vjp<NF, D, DIR>(pm, WL, L, rhoLb, useL ? Gamb : 0.0, useL ? Pib : 0.0, pLb, unLb, useL ? Eb : 0.0,
                                cLb, WLb);

@@ -112,21 +112,17 @@ int hip_fail(mfc_ctx* c, hipError_t e, const char* where) {
 
 int ensure_vjp_scratch(mfc_ctx* c) {
   if (c->vjp.G) return MFC_OK;
-  long long maxfaces = 0, maxlines = 0;
+  long long maxfaces = 0;
   for (int d = 0; d < c->prob.ndim; ++d) {
     const long long lines = c->ncell / c->prob.n[d];
     const long long faces = lines * (c->prob.n[d] + 1);
     if (faces > maxfaces) maxfaces = faces;
-    if (lines > maxlines) maxlines = lines;
   }
-  const size_t bb_stride = (size_t)6 * c->neq * (size_t)maxlines;
   const size_t state = (size_t)c->neq * (size_t)c->ncell * sizeof(double);
   bool ok = hipMalloc((void**)&c->vjp.G, (size_t)6 * c->neq * (size_t)maxfaces * sizeof(double)) == hipSuccess &&
             hipMalloc((void**)&c->vjp.UF, (size_t)maxfaces * sizeof(double)) == hipSuccess &&
-            hipMalloc((void**)&c->vjp.BB, bb_stride * 3 * sizeof(double)) == hipSuccess &&
             hipMalloc((void**)&c->vbuf, state) == hipSuccess && hipMalloc((void**)&c->b1, state) == hipSuccess &&
             hipMalloc((void**)&c->b2, state) == hipSuccess;
-  c->vjp.bb_stride = bb_stride;
   if (!ok) {
     (void)hipGetLastError();
     c->err = "adjoint scratch allocation failed";
@@ -236,7 +232,7 @@ int mfc_create(const mfc_problem* p, mfc_ctx** out) {
   c->scal = c->partial = nullptr;
   c->flag = nullptr;
   c->timer = nullptr;
-  c->vjp = mfc::VjpScratch{nullptr, nullptr, nullptr, 0};
+  c->vjp = mfc::VjpScratch{nullptr, nullptr};
   c->vbuf = c->b1 = c->b2 = nullptr;
   if (hipGetDevice(&c->device) != hipSuccess) {
     delete c;
@@ -270,7 +266,6 @@ int mfc_destroy(mfc_ctx* c) {
   if (c->flag) (void)hipFree(c->flag);
   if (c->vjp.G) (void)hipFree(c->vjp.G);
   if (c->vjp.UF) (void)hipFree(c->vjp.UF);
-  if (c->vjp.BB) (void)hipFree(c->vjp.BB);
   if (c->vbuf) (void)hipFree(c->vbuf);
   if (c->b1) (void)hipFree(c->b1);
   if (c->b2) (void)hipFree(c->b2);

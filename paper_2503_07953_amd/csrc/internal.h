@@ -56,8 +56,6 @@ hipError_t launch_set_scalar(double* dst, double value, hipStream_t s);
 struct VjpScratch {
   double* G;          // per-face primitive cotangents of the 6 stencil positions
   double* UF;         // per-face forward face velocity
-  double* BB;         // ghost-cell cotangents, 2 sides x 3 layers x rows x lines, per axis
-  size_t bb_stride;   // doubles per axis in BB
 };
 
 hipError_t launch_rhs_vjp(int nf, int ndim, const Params& pm, const double* q, const double* rbar, double* qbar,

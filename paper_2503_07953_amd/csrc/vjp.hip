@@ -9,13 +9,15 @@
 //               ufbar = sum_j (alpha_j rbar_alpha_j)_{f-1} - (...)_f (times 1/dx),
 //               then HLLC^T and WENO^T give the primitive cotangents of the six
 //               stencil positions, stored per face;
-//   gather pass one thread per position p = -3..n+2 (interior and ghost): sums the
-//               contributions of the six faces whose stencils hold p, applies
-//               cons->prim^T at the state of p, adds the direct alpha term
-//               rbar_alpha (u_{+1/2} - u_{-1/2})/dx, and writes interior
-//               cotangents to qbar, ghost cotangents to a boundary buffer;
-//   boundary    one thread per line: adds the ghost cotangents to the interior
-//               cells they were copied from (mirror sign for slip walls).
+//   gather pass one thread per interior cell p: sums the contributions of the six
+//               faces whose stencils hold p, plus those of every ghost position
+//               that the boundary condition fills from p (mirror-flipped normal
+//               velocity cotangent for slip walls), applies cons->prim^T at the
+//               state of p, adds the direct alpha term
+//               rbar_alpha (u_{+1/2} - u_{-1/2})/dx and writes qbar.
+// A ghost holds the state of its source cell (normal momentum negated at a
+// slip wall), so the ghost's primitive cotangent reaches the source through
+// the source's own cons->prim^T once its normal-velocity entry is negated.
 #include "adjoint.h"
 #include "internal.h"
 
@@ -118,115 +120,83 @@ __global__ __launch_bounds__(128) void vjp_face_kernel(Params pm, const double* 
 }
 
 template <int NF, int D, int DIR>
-__global__ __launch_bounds__(256) void vjp_gather_kernel(Params pm, const double* __restrict__ q,
-                                                         const double* __restrict__ rbar,
-                                                         const double* __restrict__ G,
-                                                         const double* __restrict__ UF, double* __restrict__ qbar,
-                                                         double* __restrict__ BB, AxisGeom eg, AxisGeom fg,
-                                                         int accumulate) {
+__device__ __forceinline__ void add_face_terms(const double* __restrict__ G, long long nfc, const AxisGeom& fg,
+                                               int i, int j, int k, int pos, int nd, double* wb) {
   using R = Rows<NF, D>;
   constexpr int NEQ = R::NEQ;
-  const long long id = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (id >= eg.count) return;
-  const int nx = pm.n[0], ny = pm.n[1];
-  const int nd = pm.n[DIR];
-  const long long nc = pm.ncell;
-  int idx[3] = {(int)(id % eg.fx), (int)((id / eg.fx) % eg.fy), (int)(id / ((long long)eg.fx * eg.fy))};
-  const int p = idx[DIR] - 3;  // position along DIR, -3 .. nd+2
-  // faces holding p in their stencils: f = p + 3 - s, s = 0..5
-  double wb[NEQ];
-#pragma unroll
-  for (int v = 0; v < NEQ; ++v) wb[v] = 0.0;
-  const long long nfc = fg.count;
+  // faces holding position pos in their stencils: f = pos + 3 - s, s = 0..5
 #pragma unroll
   for (int s = 0; s < 6; ++s) {
-    const int f = p + 3 - s;
+    const int f = pos + 3 - s;
     if (f < 0 || f > nd) continue;
-    int fi[3] = {idx[0], idx[1], idx[2]};
+    int fi[3] = {i, j, k};
     fi[DIR] = f;
     const long long fid = ((long long)fi[2] * fg.fy + fi[1]) * fg.fx + fi[0];
 #pragma unroll
     for (int v = 0; v < NEQ; ++v) wb[v] += G[(long long)(s * NEQ + v) * nfc + fid];
   }
-  bool flip;
-  const int g = ghost_index(p, nd, pm.bc_lo[DIR], pm.bc_hi[DIR], flip);
-  int ci[3] = {idx[0], idx[1], idx[2]};
-  ci[DIR] = g;
-  const long long cell = ((long long)ci[2] * ny + ci[1]) * nx + ci[0];
+}
+
+template <int NF, int D, int DIR>
+__global__ __launch_bounds__(256) void vjp_gather_kernel(Params pm, const double* __restrict__ q,
+                                                         const double* __restrict__ rbar,
+                                                         const double* __restrict__ G,
+                                                         const double* __restrict__ UF, double* __restrict__ qbar,
+                                                         AxisGeom fg, int accumulate) {
+  using R = Rows<NF, D>;
+  constexpr int NEQ = R::NEQ;
+  const long long nc = pm.ncell;
+  const long long cell = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (cell >= nc) return;
+  const int nx = pm.n[0], ny = pm.n[1];
+  const int nd = pm.n[DIR];
+  const int i = (int)(cell % nx), j = (int)((cell / nx) % ny), k = (int)(cell / ((long long)nx * ny));
+  const int idx[3] = {i, j, k};
+  const int p = idx[DIR];
+  const long long nfc = fg.count;
+  double wb[NEQ];
+#pragma unroll
+  for (int v = 0; v < NEQ; ++v) wb[v] = 0.0;
+  add_face_terms<NF, D, DIR>(G, nfc, fg, i, j, k, p, nd, wb);
+  // ghost positions filled from this cell (only cells within three of an end,
+  // or of the far end for periodic axes, have any)
+  if (p < 3 || p >= nd - 3) {
+#pragma unroll
+    for (int gsl = 0; gsl < 6; ++gsl) {
+      const int gp = gsl < 3 ? -1 - gsl : nd + gsl - 3;
+      bool flip;
+      if (ghost_index(gp, nd, pm.bc_lo[DIR], pm.bc_hi[DIR], flip) != p) continue;
+      double wg[NEQ];
+#pragma unroll
+      for (int v = 0; v < NEQ; ++v) wg[v] = 0.0;
+      add_face_terms<NF, D, DIR>(G, nfc, fg, i, j, k, gp, nd, wg);
+      if (flip) wg[R::MOM + DIR] = -wg[R::MOM + DIR];
+#pragma unroll
+      for (int v = 0; v < NEQ; ++v) wb[v] += wg[v];
+    }
+  }
   double U[NEQ], Ub[NEQ];
 #pragma unroll
   for (int v = 0; v < NEQ; ++v) {
     U[v] = q[v * nc + cell];
     Ub[v] = 0.0;
   }
-  if (flip) U[R::MOM + DIR] = -U[R::MOM + DIR];
   cons_to_prim_vjp<NF, D>(pm, U, wb, Ub);
-  if (p >= 0 && p < nd) {
-    if constexpr (NF == 2) {
-      int f0[3] = {idx[0], idx[1], idx[2]};
-      f0[DIR] = p;
-      const long long fid0 = ((long long)f0[2] * fg.fy + f0[1]) * fg.fx + f0[0];
-      int f1[3] = {idx[0], idx[1], idx[2]};
-      f1[DIR] = p + 1;
-      const long long fid1 = ((long long)f1[2] * fg.fy + f1[1]) * fg.fx + f1[0];
-      const double div = pm.inv_dx[DIR] * (UF[fid1] - UF[fid0]);
+  if constexpr (NF == 2) {
+    int f0[3] = {i, j, k};
+    f0[DIR] = p;
+    const long long fid0 = ((long long)f0[2] * fg.fy + f0[1]) * fg.fx + f0[0];
+    int f1[3] = {i, j, k};
+    f1[DIR] = p + 1;
+    const long long fid1 = ((long long)f1[2] * fg.fy + f1[1]) * fg.fx + f1[0];
+    const double div = pm.inv_dx[DIR] * (UF[fid1] - UF[fid0]);
 #pragma unroll
-      for (int a = 0; a < 2; ++a) Ub[R::ALPHA + a] += rbar[(R::ALPHA + a) * nc + cell] * div;
-    }
-#pragma unroll
-    for (int v = 0; v < NEQ; ++v) {
-      const long long e = v * nc + cell;
-      qbar[e] = accumulate ? qbar[e] + Ub[v] : Ub[v];
-    }
-  } else {
-    if (flip) Ub[R::MOM + DIR] = -Ub[R::MOM + DIR];
-    const int side = p < 0 ? 0 : 1;
-    const int layer = p < 0 ? -1 - p : p - nd;
-    const long long nlines = nc / nd;
-    const int line = line_of<DIR>(idx[0], idx[1], idx[2], nx, ny);
-#pragma unroll
-    for (int v = 0; v < NEQ; ++v) BB[((long long)((side * 3 + layer) * NEQ + v)) * nlines + line] = Ub[v];
+    for (int a = 0; a < 2; ++a) Ub[R::ALPHA + a] += rbar[(R::ALPHA + a) * nc + cell] * div;
   }
-}
-
-template <int NF, int D, int DIR>
-__global__ __launch_bounds__(256) void vjp_boundary_kernel(Params pm, const double* __restrict__ BB,
-                                                           double* __restrict__ qbar) {
-  using R = Rows<NF, D>;
-  constexpr int NEQ = R::NEQ;
-  const int nx = pm.n[0], ny = pm.n[1], nz = pm.n[2];
-  const int nd = pm.n[DIR];
-  const long long nc = pm.ncell;
-  const long long nlines = nc / nd;
-  const long long line = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (line >= nlines) return;
-  int a0, a1;  // the two fixed coordinates of the line
-  if constexpr (DIR == 0) {
-    a0 = (int)(line % ny);
-    a1 = (int)(line / ny);
-  } else if constexpr (DIR == 1) {
-    a0 = (int)(line % nx);
-    a1 = (int)(line / nx);
-  } else {
-    a0 = (int)(line % nx);
-    a1 = (int)(line / nx);
-  }
-  (void)nz;
-  for (int side = 0; side < 2; ++side) {
-    for (int layer = 0; layer < 3; ++layer) {
-      const int p = side == 0 ? -1 - layer : nd + layer;
-      bool flip;
-      const int g = ghost_index(p, nd, pm.bc_lo[DIR], pm.bc_hi[DIR], flip);
-      long long cell;
-      if constexpr (DIR == 0) cell = ((long long)a1 * ny + a0) * nx + g;
-      else if constexpr (DIR == 1) cell = ((long long)a1 * ny + g) * nx + a0;
-      else cell = ((long long)g * ny + a1) * nx + a0;
 #pragma unroll
-      for (int v = 0; v < NEQ; ++v) {
-        const long long e = v * nc + cell;
-        qbar[e] += BB[((long long)((side * 3 + layer) * NEQ + v)) * nlines + line];
-      }
-    }
+  for (int v = 0; v < NEQ; ++v) {
+    const long long e = v * nc + cell;
+    qbar[e] = accumulate ? qbar[e] + Ub[v] : Ub[v];
   }
 }
 
@@ -235,22 +205,12 @@ static hipError_t launch_axis_vjp(const Params& pm, const double* q, const doubl
                                   const VjpScratch& sc, bool accumulate, hipStream_t s) {
   AxisGeom fg{pm.n[0] + (DIR == 0), pm.n[1] + (DIR == 1), pm.n[2] + (DIR == 2), 0};
   fg.count = (long long)fg.fx * fg.fy * fg.fz;
-  AxisGeom eg{pm.n[0] + 6 * (DIR == 0), pm.n[1] + 6 * (DIR == 1), pm.n[2] + 6 * (DIR == 2), 0};
-  eg.count = (long long)eg.fx * eg.fy * eg.fz;
   hipLaunchKernelGGL((vjp_face_kernel<NF, D, DIR>), dim3((unsigned)((fg.count + 127) / 128)), dim3(128), 0, s, pm, q,
                      rbar, sc.G, sc.UF, fg);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((vjp_gather_kernel<NF, D, DIR>), dim3((unsigned)((eg.count + 255) / 256)), dim3(256), 0, s, pm,
-                     q, rbar, sc.G, sc.UF, qbar, sc.BB + (size_t)DIR * sc.bb_stride, eg, fg, accumulate ? 1 : 0);
-  return hipGetLastError();
-}
-
-template <int NF, int D, int DIR>
-static hipError_t launch_axis_boundary(const Params& pm, double* qbar, const VjpScratch& sc, hipStream_t s) {
-  const long long nlines = pm.ncell / pm.n[DIR];
-  hipLaunchKernelGGL((vjp_boundary_kernel<NF, D, DIR>), dim3((unsigned)((nlines + 255) / 256)), dim3(256), 0, s, pm,
-                     sc.BB + (size_t)DIR * sc.bb_stride, qbar);
+  hipLaunchKernelGGL((vjp_gather_kernel<NF, D, DIR>), dim3((unsigned)((pm.ncell + 255) / 256)), dim3(256), 0, s, pm,
+                     q, rbar, sc.G, sc.UF, qbar, fg, accumulate ? 1 : 0);
   return hipGetLastError();
 }
 
@@ -262,9 +222,6 @@ static hipError_t launch_rhs_vjp_t(const Params& pm, const double* q, const doub
   e = launch_axis_vjp<NF, D, 0>(pm, q, rbar, qbar, sc, accumulate, s);
   if (e == hipSuccess && D > 1) e = launch_axis_vjp<NF, D, (D > 1 ? 1 : 0)>(pm, q, rbar, qbar, sc, true, s);
   if (e == hipSuccess && D > 2) e = launch_axis_vjp<NF, D, (D > 2 ? 2 : 0)>(pm, q, rbar, qbar, sc, true, s);
-  if (e == hipSuccess) e = launch_axis_boundary<NF, D, 0>(pm, qbar, sc, s);
-  if (e == hipSuccess && D > 1) e = launch_axis_boundary<NF, D, (D > 1 ? 1 : 0)>(pm, qbar, sc, s);
-  if (e == hipSuccess && D > 2) e = launch_axis_boundary<NF, D, (D > 2 ? 2 : 0)>(pm, qbar, sc, s);
   if (tm) tm->end(KIND_VJP, s);
   return e;
 }
