@@ -147,6 +147,19 @@ int mfc_rhs_vjp(mfc_ctx* ctx, const void* q, const void* rhs_bar, void* q_bar, i
 int mfc_step_vjp(mfc_ctx* ctx, const void* q_n, double dt, const void* qnp1_bar, void* qn_bar,
                  void* hip_stream);
 
+/* The fixed-dt SSP-RK3 step of mfc_step (q advanced in place) that also writes
+ * its two stage states, q1 = q + dt L(q) and q2 = 3/4 q + 1/4 (q1 + dt L(q1))
+ * (Sec. 3.4), to the caller's arrays q1 and q2 (same layout as q, distinct from
+ * q and from each other).  Used to replay a checkpointed segment once and hand
+ * its stages to mfc_step_vjp_stages.  FP64 contexts. */
+int mfc_step_save_stages(mfc_ctx* ctx, void* q, double dt, void* q1, void* q2, void* hip_stream);
+
+/* mfc_step_vjp with the stage states of the step from q_n supplied (as written
+ * by mfc_step_save_stages for the same q_n and dt), so that they are not
+ * recomputed.  qn_bar must alias none of the inputs. */
+int mfc_step_vjp_stages(mfc_ctx* ctx, const void* q_n, const void* q1, const void* q2, double dt,
+                        const void* qnp1_bar, void* qn_bar, void* hip_stream);
+
 /* q_bar (+)= (dw/dq)^T w_bar for the conversion of mfc_cons_to_prim at q. */
 int mfc_cons_to_prim_vjp(mfc_ctx* ctx, const void* q, const void* w_bar, void* q_bar, int accumulate,
                          void* hip_stream);

@@ -61,6 +61,8 @@ SIGNATURES = {
     "mfc_get_timing": (_I, [_V, _V, _V]),
     "mfc_rhs_vjp": (_I, [_V, _V, _V, _V, _I, _V]),
     "mfc_step_vjp": (_I, [_V, _V, _D, _V, _V, _V]),
+    "mfc_step_save_stages": (_I, [_V, _V, _D, _V, _V, _V]),
+    "mfc_step_vjp_stages": (_I, [_V, _V, _V, _V, _D, _V, _V, _V]),
     "mfc_cons_to_prim_vjp": (_I, [_V, _V, _V, _V, _I, _V]),
     "mfc_prim_to_cons_vjp": (_I, [_V, _V, _V, _V, _I, _V]),
 }

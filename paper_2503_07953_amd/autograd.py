@@ -109,16 +109,20 @@ class _Rollout(torch.autograd.Function):
         starts = sorted(ctx.checkpoints)
         for seg_start in reversed(starts):
             seg_end = min(seg_start + ctx.every, ctx.nsteps)
-            # recompute q^{seg_start} .. q^{seg_end}
-            states = [ctx.checkpoints[seg_start]]
+            # replay the segment once, keeping every step's input and stage states
+            states, stages = [ctx.checkpoints[seg_start]], []
             for _ in range(seg_start, seg_end):
                 nxt = states[-1].clone()
-                S.step(nxt, dt_fixed=ctx.dt)
+                q1, q2 = torch.empty_like(nxt), torch.empty_like(nxt)
+                S.step_save_stages(nxt, ctx.dt, q1, q2)
                 states.append(nxt)
+                stages.append((q1, q2))
             for n in range(seg_end, seg_start, -1):
                 # inject dJ/dq^n, then pull through step n-1 -> n
-                S.cons_to_prim_vjp(states[n - seg_start], wb, out=qbar, accumulate=True)
-                qbar = S.step_vjp(states[n - seg_start - 1], ctx.dt, qbar)
+                k = n - seg_start
+                S.cons_to_prim_vjp(states[k], wb, out=qbar, accumulate=True)
+                q1, q2 = stages[k - 1]
+                qbar = S.step_vjp_stages(states[k - 1], q1, q2, ctx.dt, qbar)
         return qbar, None, None, None, None, None
 
 

@@ -218,7 +218,8 @@ __host__ __device__ __forceinline__ void side_scalars_vjp(const Params& pm, cons
 
 template <int NF, int D, int DIR>
 __host__ __device__ __forceinline__ void hllc_vjp(const Params& pm, const double* WL, const double* WR,
-                                                  const double* Fb, double ufb, double* WLb, double* WRb) {
+                                                  const double* Fb, double ufb, double* WLb, double* WRb,
+                                                  double* uf_out = nullptr) {
   using R = Rows<NF, D>;
   constexpr int NEQ = R::NEQ;
   SideState<NF, D> L, Rs;
@@ -250,6 +251,7 @@ __host__ __device__ __forceinline__ void hllc_vjp(const Params& pm, const double
   const double KE = useL ? L.E : Rs.E;
   const double SK = useL ? SL : SR;
   const double uf = star ? Sstar : Kun;
+  if (uf_out) *uf_out = uf;
 
   // side-K scalar cotangents
   double rhob = 0.0, Gamb = 0.0, Pib = 0.0, pb = 0.0, unb = 0.0, Eb = 0.0;

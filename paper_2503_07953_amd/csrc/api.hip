@@ -370,6 +370,19 @@ hipError_t step_t(mfc_ctx* c, Real* q, double cfl, double dt_fixed, double t_rem
   e = mfc::launch_rhs<Real>(nf, nd, c->pm, q2, acc, q, q, st, true, c->flag, s, c->timer);
   return e;
 }
+// Reverse sweep of one SSP-RK3 step given its stage states.
+hipError_t step_reverse(mfc_ctx* c, const double* qn, const double* q1, const double* q2, double dt,
+                        const double* qnp1_bar, double* qn_bar, hipStream_t s) {
+  const int nf = c->prob.num_fluids, nd = c->prob.ndim;
+  const long long n = (long long)c->neq * c->ncell;
+  hipError_t e = mfc::launch_rhs_vjp(nf, nd, c->pm, q2, qnp1_bar, c->vbuf, c->vjp, false, s, c->timer);
+  if (e == hipSuccess) e = mfc::launch_adj_stage(3, n, dt, qnp1_bar, c->vbuf, c->b2, qn_bar, s);
+  if (e == hipSuccess) e = mfc::launch_rhs_vjp(nf, nd, c->pm, q1, c->b2, c->vbuf, c->vjp, false, s, c->timer);
+  if (e == hipSuccess) e = mfc::launch_adj_stage(2, n, dt, c->b2, c->vbuf, c->b1, qn_bar, s);
+  if (e == hipSuccess) e = mfc::launch_rhs_vjp(nf, nd, c->pm, qn, c->b1, c->vbuf, c->vjp, false, s, c->timer);
+  if (e == hipSuccess) e = mfc::launch_adj_stage(1, n, dt, c->b1, c->vbuf, nullptr, qn_bar, s);
+  return e;
+}
 }  // namespace
 
 extern "C" {
@@ -433,22 +446,53 @@ int mfc_step_vjp(mfc_ctx* c, const void* q_n, double dt, const void* qnp1_bar, v
   double* q1 = (double*)c->q1;
   double* q2 = (double*)c->q2;
   double* acc = (double*)c->acc;
-  const long long n = (long long)c->neq * c->ncell;
   // recompute the stage states with the same dt
   mfc::StageArgs st{1, dt, nullptr};
   hipError_t e = mfc::launch_rhs<double>(nf, nd, c->pm, qn, acc, qn, q1, st, true, c->flag, s, c->timer);
   st.stage = 2;
   if (e == hipSuccess) e = mfc::launch_rhs<double>(nf, nd, c->pm, q1, acc, qn, q2, st, true, c->flag, s, c->timer);
-  // reverse sweep
-  if (e == hipSuccess)
-    e = mfc::launch_rhs_vjp(nf, nd, c->pm, q2, (const double*)qnp1_bar, c->vbuf, c->vjp, false, s, c->timer);
-  if (e == hipSuccess)
-    e = mfc::launch_adj_stage(3, n, dt, (const double*)qnp1_bar, c->vbuf, c->b2, (double*)qn_bar, s);
-  if (e == hipSuccess) e = mfc::launch_rhs_vjp(nf, nd, c->pm, q1, c->b2, c->vbuf, c->vjp, false, s, c->timer);
-  if (e == hipSuccess) e = mfc::launch_adj_stage(2, n, dt, c->b2, c->vbuf, c->b1, (double*)qn_bar, s);
-  if (e == hipSuccess) e = mfc::launch_rhs_vjp(nf, nd, c->pm, qn, c->b1, c->vbuf, c->vjp, false, s, c->timer);
-  if (e == hipSuccess) e = mfc::launch_adj_stage(1, n, dt, c->b1, c->vbuf, nullptr, (double*)qn_bar, s);
+  if (e == hipSuccess) e = step_reverse(c, qn, q1, q2, dt, (const double*)qnp1_bar, (double*)qn_bar, s);
   return e == hipSuccess ? MFC_OK : hip_fail(c, e, "step_vjp");
+}
+
+int mfc_step_save_stages(mfc_ctx* c, void* q, double dt, void* q1, void* q2, void* stream) {
+  if (!c) return MFC_ERR_ARG;
+  if (c->prob.precision != MFC_FP64) return fail(c, MFC_ERR_UNSUPPORTED, "adjoint entry points are FP64 only");
+  int r;
+  if ((r = check_array(c, q, "q")) || (r = check_array(c, q1, "q1")) || (r = check_array(c, q2, "q2"))) return r;
+  if (!(dt > 0.0) || !(dt < 1e300)) return fail(c, MFC_ERR_ARG, "dt must be positive and finite");
+  if (q1 == q || q2 == q || q1 == q2) return fail(c, MFC_ERR_ARG, "q, q1 and q2 must be distinct");
+  hipStream_t s = (hipStream_t)stream;
+  const int nf = c->prob.num_fluids, nd = c->prob.ndim;
+  double* qq = (double*)q;
+  double* acc = (double*)c->acc;
+  mfc::StageArgs st{1, dt, nullptr};
+  hipError_t e = mfc::launch_rhs<double>(nf, nd, c->pm, qq, acc, qq, (double*)q1, st, true, c->flag, s, c->timer);
+  st.stage = 2;
+  if (e == hipSuccess)
+    e = mfc::launch_rhs<double>(nf, nd, c->pm, (const double*)q1, acc, qq, (double*)q2, st, true, c->flag, s,
+                                c->timer);
+  st.stage = 3;
+  if (e == hipSuccess)
+    e = mfc::launch_rhs<double>(nf, nd, c->pm, (const double*)q2, acc, qq, qq, st, true, c->flag, s, c->timer);
+  return e == hipSuccess ? MFC_OK : hip_fail(c, e, "step_save_stages");
+}
+
+int mfc_step_vjp_stages(mfc_ctx* c, const void* q_n, const void* q1, const void* q2, double dt,
+                        const void* qnp1_bar, void* qn_bar, void* stream) {
+  if (!c) return MFC_ERR_ARG;
+  if (c->prob.precision != MFC_FP64) return fail(c, MFC_ERR_UNSUPPORTED, "adjoint entry points are FP64 only");
+  int r;
+  if ((r = check_array(c, q_n, "q_n")) || (r = check_array(c, q1, "q1")) || (r = check_array(c, q2, "q2")) ||
+      (r = check_array(c, qnp1_bar, "qnp1_bar")) || (r = check_array(c, qn_bar, "qn_bar")))
+    return r;
+  if (!(dt > 0.0) || !(dt < 1e300)) return fail(c, MFC_ERR_ARG, "dt must be positive and finite");
+  if (qn_bar == q_n || qn_bar == qnp1_bar || qn_bar == q1 || qn_bar == q2)
+    return fail(c, MFC_ERR_ARG, "qn_bar aliases an input");
+  if ((r = ensure_vjp_scratch(c))) return r;
+  hipError_t e = step_reverse(c, (const double*)q_n, (const double*)q1, (const double*)q2, dt,
+                              (const double*)qnp1_bar, (double*)qn_bar, (hipStream_t)stream);
+  return e == hipSuccess ? MFC_OK : hip_fail(c, e, "step_vjp_stages");
 }
 
 int mfc_cons_to_prim_vjp(mfc_ctx* c, const void* q, const void* w_bar, void* q_bar, int accumulate, void* stream) {

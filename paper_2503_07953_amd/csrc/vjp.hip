@@ -35,86 +35,152 @@ __device__ __forceinline__ int line_of(int i, int j, int k, int nx, int ny) {
   else return j * nx + i;
 }
 
+// Face tile: FA consecutive faces along the axis times FB lines across it (x
+// lanes for the y and z axes, so that every load is coalesced).  The
+// primitives of the FA + 5 cells the stencils touch are converted once and
+// staged in LDS; each face thread reads its six-cell stencil from there.
+template <int DIR>
+struct FaceTile {
+  static constexpr int FA = (DIR == 0) ? 128 : 8;
+  static constexpr int FB = (DIR == 0) ? 1 : 32;
+  static constexpr int NT = FA * FB;
+  static constexpr int CA = FA + 5;  // cells f0-3 .. f0+FA+1
+};
+
+template <int DIR>
+__device__ __forceinline__ int face_lds(int v, int c, int b) {
+  using FT = FaceTile<DIR>;
+  if constexpr (DIR == 0)
+    return v * FT::CA + c;
+  else
+    return (v * FT::CA + c) * FT::FB + b;
+}
+
+template <int DIR>
+__device__ __forceinline__ long long cell_at(int pos, int i, int j, int k, int nx, int ny) {
+  if constexpr (DIR == 0)
+    return ((long long)k * ny + j) * nx + pos;
+  else if constexpr (DIR == 1)
+    return ((long long)k * ny + pos) * nx + i;
+  else
+    return ((long long)pos * ny + j) * nx + i;
+}
+
 template <int NF, int D, int DIR>
-__global__ __launch_bounds__(128) void vjp_face_kernel(Params pm, const double* __restrict__ q,
-                                                       const double* __restrict__ rbar, double* __restrict__ G,
-                                                       double* __restrict__ UF, AxisGeom fg) {
+__global__ __launch_bounds__((FaceTile<DIR>::NT)) void vjp_face_kernel(Params pm, const double* __restrict__ q,
+                                                                      const double* __restrict__ rbar,
+                                                                      double* __restrict__ G,
+                                                                      double* __restrict__ UF, AxisGeom fg) {
   using R = Rows<NF, D>;
+  using FT = FaceTile<DIR>;
   constexpr int NEQ = R::NEQ;
-  const long long id = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (id >= fg.count) return;
+  __shared__ double sw[NEQ * FT::CA * FT::FB];
   const int nx = pm.n[0], ny = pm.n[1];
   const int nd = pm.n[DIR];
   const long long nc = pm.ncell;
-  const int i = (int)(id % fg.fx);
-  const int j = (int)((id / fg.fx) % fg.fy);
-  const int k = (int)(id / ((long long)fg.fx * fg.fy));
-  int idx[3] = {i, j, k};
-  const int f = idx[DIR];
-
-  double Wc[6][NEQ];
-  double rb[2][NEQ];
-#pragma unroll
-  for (int s = 0; s < 6; ++s) {
-    bool flip;
-    const int g = ghost_index(f - 3 + s, nd, pm.bc_lo[DIR], pm.bc_hi[DIR], flip);
-    int id2[3] = {i, j, k};
-    id2[DIR] = g;
-    const long long cell = ((long long)id2[2] * ny + id2[1]) * nx + id2[0];
-    double U[NEQ];
-#pragma unroll
-    for (int v = 0; v < NEQ; ++v) U[v] = q[v * nc + cell];
-    if (flip) U[R::MOM + DIR] = -U[R::MOM + DIR];
-    cons_to_prim<NF, D>(pm, U, Wc[s]);
-    if (s == 2 || s == 3) {
-      const int c = f - 3 + s;  // cells f-1 and f
-      const bool inside = c >= 0 && c < nd;
-#pragma unroll
-      for (int v = 0; v < NEQ; ++v) rb[s - 2][v] = inside ? rbar[v * nc + cell] : 0.0;
+  // this thread's face (a along the axis, b across it) and its line
+  int a, b, f0, i, j, k, ibase;
+  if constexpr (DIR == 0) {
+    a = threadIdx.x;
+    b = 0;
+    f0 = blockIdx.x * FT::FA;
+    ibase = 0;
+    i = f0 + a;
+    j = blockIdx.y;
+    k = blockIdx.z;
+  } else {
+    b = threadIdx.x;
+    a = threadIdx.y;
+    f0 = blockIdx.y * FT::FA;
+    ibase = blockIdx.x * FT::FB;
+    i = ibase + b;
+    if constexpr (DIR == 1) {
+      j = f0 + a;
+      k = blockIdx.z;
+    } else {
+      j = blockIdx.z;
+      k = f0 + a;
     }
   }
+  // stage the primitives of positions f0-3 .. f0+FA+1 (ghosts remapped)
+  const int tid = threadIdx.y * blockDim.x + threadIdx.x;
+  for (int e = tid; e < FT::CA * FT::FB; e += FT::NT) {
+    const int c = (DIR == 0) ? e : e / FT::FB;
+    const int bb = (DIR == 0) ? 0 : e % FT::FB;
+    const int pos = f0 - 3 + c;
+    const int ii = ibase + bb;
+    double Wv[NEQ];
+    if (pos >= -3 && pos <= nd + 2 && (DIR == 0 || ii < nx)) {
+      bool flip;
+      const int g = ghost_index(pos, nd, pm.bc_lo[DIR], pm.bc_hi[DIR], flip);
+      const long long cell = cell_at<DIR>(g, ii, j, k, nx, ny);
+      double U[NEQ];
+#pragma unroll
+      for (int v = 0; v < NEQ; ++v) U[v] = q[v * nc + cell];
+      if (flip) U[R::MOM + DIR] = -U[R::MOM + DIR];
+      cons_to_prim<NF, D>(pm, U, Wv);
+    } else {
+#pragma unroll
+      for (int v = 0; v < NEQ; ++v) Wv[v] = 0.0;
+    }
+#pragma unroll
+    for (int v = 0; v < NEQ; ++v) sw[face_lds<DIR>(v, c, bb)] = Wv[v];
+  }
+  __syncthreads();
+  const int f = f0 + a;
+  if (f > nd || (DIR != 0 && i >= nx)) return;
+  const long long id = ((long long)k * fg.fy + j) * fg.fx + i;
+  // stencil slot s = 0..5 holds position f-3+s
+  auto Ws = [&](int s, int v) -> double { return sw[face_lds<DIR>(v, a + s, b)]; };
+
+  // face cotangents: Fbar = (rbar_f - rbar_{f-1})/dx over interior cells, and
+  // ufbar from the alpha source of the two cells sharing the face
+  const double inv_dx = pm.inv_dx[DIR];
+  const bool in0 = f - 1 >= 0, in1 = f < nd;
+  const long long c0 = cell_at<DIR>(in0 ? f - 1 : 0, i, j, k, nx, ny);
+  const long long c1 = cell_at<DIR>(in1 ? f : 0, i, j, k, nx, ny);
+  double Fb[NEQ];
+  double ufb = 0.0;
+#pragma unroll
+  for (int v = 0; v < NEQ; ++v) {
+    const double r0 = in0 ? rbar[v * nc + c0] : 0.0;
+    const double r1 = in1 ? rbar[v * nc + c1] : 0.0;
+    Fb[v] = inv_dx * (r1 - r0);
+    if constexpr (NF == 2) {
+      if (v >= R::ALPHA) ufb += Ws(2, v) * r0 - Ws(3, v) * r1;
+    }
+  }
+  ufb *= inv_dx;
+
   double WL[NEQ], WR[NEQ];
 #pragma unroll
   for (int v = 0; v < NEQ; ++v) {
     double l, r, t;
-    weno5_js(Wc[0][v], Wc[1][v], Wc[2][v], Wc[3][v], Wc[4][v], pm.eps, l, t);
-    weno5_js(Wc[1][v], Wc[2][v], Wc[3][v], Wc[4][v], Wc[5][v], pm.eps, t, r);
+    weno5_js(Ws(0, v), Ws(1, v), Ws(2, v), Ws(3, v), Ws(4, v), pm.eps, l, t);
+    weno5_js(Ws(1, v), Ws(2, v), Ws(3, v), Ws(4, v), Ws(5, v), pm.eps, t, r);
     WL[v] = l;
     WR[v] = r;
-  }
-  double F[NEQ], uf;
-  (void)hllc<NF, D, DIR, double>(pm, WL, WR, F, uf);
-
-  const double inv_dx = pm.inv_dx[DIR];
-  double Fb[NEQ];
-#pragma unroll
-  for (int v = 0; v < NEQ; ++v) Fb[v] = inv_dx * (rb[1][v] - rb[0][v]);
-  double ufb = 0.0;
-  if constexpr (NF == 2) {
-#pragma unroll
-    for (int a = 0; a < 2; ++a)
-      ufb += Wc[2][R::ALPHA + a] * rb[0][R::ALPHA + a] - Wc[3][R::ALPHA + a] * rb[1][R::ALPHA + a];
-    ufb *= inv_dx;
   }
   double WLb[NEQ], WRb[NEQ];
 #pragma unroll
   for (int v = 0; v < NEQ; ++v) WLb[v] = WRb[v] = 0.0;
-  hllc_vjp<NF, D, DIR>(pm, WL, WR, Fb, ufb, WLb, WRb);
+  double uf;
+  hllc_vjp<NF, D, DIR>(pm, WL, WR, Fb, ufb, WLb, WRb, &uf);
 
-  const long long nf = fg.count;
+  const long long nfc = fg.count;
 #pragma unroll
   for (int v = 0; v < NEQ; ++v) {
     double g[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-    weno_left_vjp(Wc[0][v], Wc[1][v], Wc[2][v], Wc[3][v], Wc[4][v], pm.eps, WLb[v], g);
+    weno_left_vjp(Ws(0, v), Ws(1, v), Ws(2, v), Ws(3, v), Ws(4, v), pm.eps, WLb[v], g);
     double gr[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-    weno_left_vjp(Wc[5][v], Wc[4][v], Wc[3][v], Wc[2][v], Wc[1][v], pm.eps, WRb[v], gr);
+    weno_left_vjp(Ws(5, v), Ws(4, v), Ws(3, v), Ws(2, v), Ws(1, v), pm.eps, WRb[v], gr);
     g[1] += gr[4];
     g[2] += gr[3];
     g[3] += gr[2];
     g[4] += gr[1];
     g[5] += gr[0];
 #pragma unroll
-    for (int s = 0; s < 6; ++s) G[(long long)(s * NEQ + v) * nf + id] = g[s];
+    for (int s = 0; s < 6; ++s) G[(long long)(s * NEQ + v) * nfc + id] = g[s];
   }
   UF[id] = uf;
 }
@@ -205,8 +271,18 @@ static hipError_t launch_axis_vjp(const Params& pm, const double* q, const doubl
                                   const VjpScratch& sc, bool accumulate, hipStream_t s) {
   AxisGeom fg{pm.n[0] + (DIR == 0), pm.n[1] + (DIR == 1), pm.n[2] + (DIR == 2), 0};
   fg.count = (long long)fg.fx * fg.fy * fg.fz;
-  hipLaunchKernelGGL((vjp_face_kernel<NF, D, DIR>), dim3((unsigned)((fg.count + 127) / 128)), dim3(128), 0, s, pm, q,
-                     rbar, sc.G, sc.UF, fg);
+  using FT = FaceTile<DIR>;
+  dim3 grid, block;
+  if constexpr (DIR == 0) {
+    grid = dim3((unsigned)((pm.n[0] + 1 + FT::FA - 1) / FT::FA), (unsigned)pm.n[1], (unsigned)pm.n[2]);
+    block = dim3(FT::FA, 1, 1);
+  } else {
+    const int across = (DIR == 1) ? pm.n[2] : pm.n[1];
+    grid = dim3((unsigned)((pm.n[0] + FT::FB - 1) / FT::FB), (unsigned)((pm.n[DIR] + 1 + FT::FA - 1) / FT::FA),
+                (unsigned)across);
+    block = dim3(FT::FB, FT::FA, 1);
+  }
+  hipLaunchKernelGGL((vjp_face_kernel<NF, D, DIR>), grid, block, 0, s, pm, q, rbar, sc.G, sc.UF, fg);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL((vjp_gather_kernel<NF, D, DIR>), dim3((unsigned)((pm.ncell + 255) / 256)), dim3(256), 0, s, pm,

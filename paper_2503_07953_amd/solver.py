@@ -147,6 +147,26 @@ class Solver:
                     "mfc_step_vjp")
         return o
 
+    def step_save_stages(self, q, dt, q1, q2):
+        """Fixed-dt step of q in place; its two stage states are written to q1, q2."""
+        qq = self._arr(q, "q")
+        a = self._arr(q1, "q1")
+        b = self._arr(q2, "q2")
+        self._check(self.lib.mfc_step_save_stages(self.ctx, _ptr(qq), float(dt), _ptr(a), _ptr(b), _stream()),
+                    "mfc_step_save_stages")
+        return qq
+
+    def step_vjp_stages(self, q_n, q1, q2, dt, qnp1_bar, out=None):
+        """step_vjp with the step's stage states supplied (from step_save_stages)."""
+        q = self._arr(q_n, "q_n")
+        a = self._arr(q1, "q1")
+        b = self._arr(q2, "q2")
+        g = self._arr(qnp1_bar, "qnp1_bar")
+        o = self._out(out, False)
+        self._check(self.lib.mfc_step_vjp_stages(self.ctx, _ptr(q), _ptr(a), _ptr(b), float(dt), _ptr(g), _ptr(o),
+                                                 _stream()), "mfc_step_vjp_stages")
+        return o
+
     def cons_to_prim_vjp(self, q, w_bar, out=None, accumulate=False):
         q = self._arr(q)
         wb = self._arr(w_bar, "w_bar")

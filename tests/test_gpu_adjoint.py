@@ -336,3 +336,26 @@ def test_adjoint_256_against_central_differences_at_fd_resolution():
     assert np.median(err) <= 0.1
     assert err.max() <= 0.5
     assert cos >= 0.95
+
+
+def test_step_with_saved_stages_matches_step_and_step_vjp_bitwise():
+    """mfc_step_save_stages advances exactly as mfc_step (fixed dt) and
+    mfc_step_vjp_stages on its stages returns exactly mfc_step_vjp."""
+    c = W.random_case(2, (70, 45), nf=2, seed=21, bc=(W.EXTRAP, W.SLIPWALL))
+    S = _solver(c)
+    q = S.prim_to_cons(S.to_device(c.w))
+    dt = 0.4 / S.max_signal(q).item()
+    a = q.clone()
+    S.step(a, dt_fixed=dt)
+    b = q.clone()
+    q1, q2 = torch.empty_like(q), torch.empty_like(q)
+    S.step_save_stages(b, dt, q1, q2)
+    assert torch.equal(a, b)
+    lam = torch.from_numpy(np.random.default_rng(4).normal(size=q.shape)).cuda()
+    g1 = S.step_vjp(q, dt, lam)
+    g2 = S.step_vjp_stages(q, q1, q2, dt, lam)
+    S.check()
+    assert torch.equal(g1, g2)
+    from paper_2503_07953_amd import _lib as L
+    with pytest.raises(L.MfcError):
+        S.step_save_stages(b, dt, q1, q1)
