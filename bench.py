@@ -133,6 +133,70 @@ def adjoint_cost(n=256, steps=200, every=20):
             "adjoint_over_forward": round((tfb - tf) / tf, 3), "total_over_forward": round(tfb / tf, 3)}
 
 
+def roofline_of(kinds, neq, esize, ndim, ncell):
+    """Roofline of the kernel kind with the largest total time: algorithmic
+    bytes per launch over its average launch duration (HIP events)."""
+    dom = max((k for k in kinds if kinds[k][1] > 0), key=lambda k: kinds[k][0])
+    avg_ms = kinds[dom][0] / kinds[dom][1]
+    bpc = pass_bytes_per_cell(dom, neq, esize, ndim)
+    achieved = bpc * ncell / (avg_ms * 1e-3) / 1e9
+    return {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "avg_launch_ms": round(avg_ms, 5),
+            "alg_bytes_per_cell": round(bpc, 2)}
+
+
+def field_group_errors(a, b, nf, ndim):
+    """Max-relative L-inf and relative L2 error of a against b per conservative
+    field (each partial density, the momentum vector, the energy, each alpha)."""
+    import numpy as np
+    groups = [[i] for i in range(nf)] + [list(range(nf, nf + ndim))] + [[nf + ndim]] + \
+        [[nf + ndim + 1 + j] for j in range(nf if nf > 1 else 0)]
+    linf, l2 = [], []
+    for g in groups:
+        da = np.sqrt(((a[g] - b[g]) ** 2).sum(axis=0))
+        nb = np.sqrt((b[g] ** 2).sum(axis=0))
+        linf.append(float(f"{da.max() / nb.max():.3e}"))
+        l2.append(float(f"{np.linalg.norm(da) / np.linalg.norm(nb):.3e}"))
+    return linf, l2
+
+
+def periodic_slab_leg(n=512, steps=100, warmup=2):
+    """The periodic air-water slab, n^3, `steps` CFL steps in the FP32 form and
+    on the FP64 path: grind time, dominant-kernel roofline, FP32 error."""
+    import torch
+
+    import workloads as W
+    from paper_2503_07953_amd.solver import Solver
+    t_ic = time.time()
+    c = W.periodic_slab(n, steps=steps)
+    log(f"initial condition {c.name}: {time.time() - t_ic:.1f}s")
+    out = {"workload": f"periodic air-water slab {n}^3, k^-2 velocity at rms Mach 0.3, {steps} CFL steps"}
+    finals = {}
+    for prec, esize in (("fp64", 8), ("fp32", 4)):
+        S = Solver.from_case(c, precision=prec)
+        q = S.prim_to_cons(S.to_device(c.w))
+        q0 = q.clone()
+        for _ in range(warmup):     # warm-up steps, then restart from the initial state
+            S.step(q, cfl=c.cfl)
+        q.copy_(q0)
+        del q0
+        ms, kinds = time_steps(S, q, steps, 0, c.cfl)
+        g = ms / steps * 1e6 / (c.ncell * 3)
+        out[prec] = {"ns_per_cell_stage": round(g, 5), "ms_per_step": round(ms / steps, 4),
+                     "roofline": roofline_of(kinds, c.neq, esize, 3, c.ncell)}
+        finals[prec] = q.double().cpu().numpy()
+        log(f"slab {prec}: {out[prec]}")
+        del S, q
+        torch.cuda.empty_cache()
+    out["fp32_speedup_vs_fp64"] = round(out["fp64"]["ns_per_cell_stage"] / out["fp32"]["ns_per_cell_stage"], 3)
+    linf, l2 = field_group_errors(finals["fp32"], finals["fp64"], 2, 3)
+    out["fp32_error_vs_fp64"] = {"after_steps": steps,
+                                 "fields": ["alpha1 rho1", "alpha2 rho2", "momentum", "rho E", "alpha1", "alpha2"],
+                                 "linf": linf, "l2": l2}
+    del finals
+    return out
+
+
 def shock_cylinder_grind(n=512, steps=20, warmup=3):
     import torch
 
@@ -155,6 +219,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-extra", action="store_true", help="skip the 512^2 shock-cylinder grind time")
+    ap.add_argument("--no-slab", action="store_true", help="skip the 512^3 periodic-slab FP32/FP64 leg")
+    ap.add_argument("--slab-n", type=int, default=512)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 1 GiB device-to-device copy (counter calibration)")
     args = ap.parse_args()
@@ -194,20 +260,13 @@ def main():
     log(f"fp64: {ms_step:.3f} ms/step, {grind:.4f} ns/cell/stage, kinds {kinds}")
 
     # dominant kernel roofline
-    dom = max((k for k in kinds if kinds[k][1] > 0), key=lambda k: kinds[k][0])
-    avg_ms = kinds[dom][0] / kinds[dom][1]
-    bpc = pass_bytes_per_cell(dom, neq, 8, case.ndim)
-    bytes_launch = bpc * ncell
-    achieved = bytes_launch / (avg_ms * 1e-3) / 1e9
+    roofline = roofline_of(kinds, neq, 8, case.ndim, ncell)
+    dom, avg_ms = roofline["kernel"], roofline["avg_launch_ms"]
     flops_cell = FLOPS_PASS_3D2F + (FLOPS_STAGE_UPDATE if dom == "pass_z" else 0)
     tflops = flops_cell * ncell / (avg_ms * 1e-3) / 1e12
+    roofline["fp64_tflops_alg"] = round(tflops, 3)
+    roofline["fp64_frac_alg"] = round(tflops / FP64_PEAK_TFLOPS, 4)
     stage_bytes = (8.0 / 3.0) * neq * 8  # per cell-stage, ideal fused path
-    roofline = {
-        "bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-        "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-        "avg_launch_ms": round(avg_ms, 5), "alg_bytes_per_cell": round(bpc, 2),
-        "fp64_tflops_alg": round(tflops, 3), "fp64_frac_alg": round(tflops / FP64_PEAK_TFLOPS, 4),
-    }
 
     # ---------------- FP32 form ----------------
     fp32 = None
@@ -216,22 +275,11 @@ def main():
         q32 = S32.prim_to_cons(S32.to_device(case.w))
         ms32, kinds32 = time_steps(S32, q32, args.steps, args.warmup, cfl)
         g32 = ms32 / args.steps * 1e6 / (ncell * 3)
-        a = q32.double().cpu().numpy()
-        b = q.cpu().numpy()
-        # per conservative field: each partial density, the momentum vector,
-        # the energy, each volume fraction (relative to the field maximum)
-        groups = [[0], [1], [2, 3, 4], [5], [6], [7]]
-        linf, l2 = [], []
-        for g in groups:
-            da = np.sqrt(((a[g] - b[g]) ** 2).sum(axis=0))
-            nb = np.sqrt((b[g] ** 2).sum(axis=0))
-            linf.append(float(da.max() / nb.max()))
-            l2.append(float(np.linalg.norm(da) / np.linalg.norm(nb)))
+        linf, l2 = field_group_errors(q32.double().cpu().numpy(), q.cpu().numpy(), 2, 3)
         fp32 = {"ns_per_cell_stage": round(g32, 5), "speedup_vs_fp64": round(grind / g32, 3),
                 "steps_compared": args.warmup + args.steps,
                 "fields": ["alpha1 rho1", "alpha2 rho2", "momentum", "rho E", "alpha1", "alpha2"],
-                "error_vs_fp64_linf": [float(f"{x:.3e}") for x in linf],
-                "error_vs_fp64_l2": [float(f"{x:.3e}") for x in l2]}
+                "error_vs_fp64_linf": linf, "error_vs_fp64_l2": l2}
         log(f"fp32: {g32:.4f} ns/cell/stage, speedup {grind / g32:.2f}, linf {linf}")
         del S32, q32
 
@@ -244,6 +292,11 @@ def main():
     if not args.no_extra:
         extra = {"shock_cylinder_512_fp64_ns_per_cell_stage": shock_cylinder_grind()}
         log(f"extra: {extra}")
+    slab = None
+    if not args.no_slab:
+        del S
+        torch.cuda.empty_cache()
+        slab = periodic_slab_leg(args.slab_n)
 
     # ---------------- CPU oracle on this host ----------------
     cpu = None
@@ -275,6 +328,7 @@ def main():
         "fp32_form": fp32,
         "adjoint_cost": adj,
         "other_workloads": extra,
+        "periodic_slab": slab,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

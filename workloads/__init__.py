@@ -90,9 +90,17 @@ def _tanh_fraction(signed_dist, width):
 
 def _two_fluid_w(alpha_water, rho_w, rho_a, vel, p):
     """Assemble the primitive rows from phase quantities (fluid 1 water)."""
-    alpha_air = 1.0 - alpha_water
-    rows = [alpha_water * rho_w, alpha_air * rho_a] + list(vel) + [p, alpha_water, alpha_air]
-    return np.ascontiguousarray(np.stack([np.broadcast_to(r, p.shape) for r in rows]).astype(np.float64))
+    nd = len(vel)
+    shape = np.broadcast(alpha_water, rho_w, rho_a, p, *vel).shape
+    w = np.empty((5 + nd,) + shape, dtype=np.float64)
+    np.multiply(alpha_water, rho_w, out=w[0])
+    np.subtract(1.0, alpha_water, out=w[4 + nd])      # alpha_air
+    np.multiply(w[4 + nd], rho_a, out=w[1])
+    for d, v in enumerate(vel):
+        w[2 + d] = v
+    w[2 + nd] = p
+    w[3 + nd] = alpha_water
+    return w
 
 
 def water_shock_state(mach: float, p0: float = 1e5):
@@ -324,13 +332,15 @@ def periodic_slab(n: int = 512, seed: int = 4, steps: int = 100, mach_rms: float
     alpha_w = e + (1 - 2 * e) * 0.5 * (np.tanh((z - zlo) / dx) - np.tanh((z - zhi) / dx))
     alpha_w = np.clip(alpha_w, e, 1 - e)
 
-    # Gaussian random velocity field with E(k) ~ k^-2 on 1 <= |k| <= kmax, solenoidal.
-    kz = np.fft.fftfreq(n, d=1.0 / n)
-    kx = np.fft.rfftfreq(n, d=1.0 / n)
-    KZ = kz[:, None, None]
-    KY = kz[None, :, None]
-    KX = kx[None, None, :]
-    kk = np.sqrt(KX ** 2 + KY ** 2 + KZ ** 2).astype(np.float32)
+    # Gaussian random velocity field with E(k) ~ k^-2 on 1 <= |k| <= kmax,
+    # solenoidal.  Coefficients are drawn only inside the |k_i| <= kmax box and
+    # zero-padded to the n^3 spectrum before the inverse FFT.
+    m = 2 * kmax + 1
+    kb = np.concatenate([np.arange(0, kmax + 1), np.arange(-kmax, 0)]).astype(np.float32)
+    KZ = kb[:, None, None]
+    KY = kb[None, :, None]
+    KX = np.arange(0, kmax + 1, dtype=np.float32)[None, None, :]
+    kk = np.sqrt(KX ** 2 + KY ** 2 + KZ ** 2)
     shell = (kk >= 1) & (kk <= kmax)
     amp = np.zeros_like(kk)
     amp[shell] = kk[shell] ** -2.0       # |u_hat| ~ sqrt(E(k) / k^2) ~ k^-2
@@ -339,21 +349,25 @@ def periodic_slab(n: int = 512, seed: int = 4, steps: int = 100, mach_rms: float
         re = rng.standard_normal(kk.shape, dtype=np.float32)
         im = rng.standard_normal(kk.shape, dtype=np.float32)
         comps.append((re + 1j * im).astype(np.complex64) * amp)
-    with np.errstate(invalid="ignore", divide="ignore"):
-        k2 = np.where(kk > 0, kk * kk, 1.0).astype(np.float32)
-        dot = (KX * comps[0] + KY * comps[1] + KZ * comps[2]) / k2
+    k2 = np.where(kk > 0, kk * kk, 1.0).astype(np.float32)
+    dot = (KX * comps[0] + KY * comps[1] + KZ * comps[2]) / k2
     comps[0] -= KX * dot
     comps[1] -= KY * dot
     comps[2] -= KZ * dot
-    del dot, k2
-    vel = [sfft.irfftn(c, s=(n, n, n), axes=(0, 1, 2), workers=-1).astype(np.float64) for c in comps]
-    del comps
+    zidx = np.concatenate([np.arange(0, kmax + 1), np.arange(n - kmax, n)])
+    vel = []
+    for cb in comps:
+        full = np.zeros((n, n, n // 2 + 1), dtype=np.complex64)
+        full[np.ix_(zidx, zidx, np.arange(kmax + 1))] = cb
+        vel.append(sfft.irfftn(full, s=(n, n, n), axes=(0, 1, 2), workers=-1))
+        del full
+    assert m == zidx.size
     rms = math.sqrt(sum(float(np.mean(v * v)) for v in vel) / 3.0)
     c_air = math.sqrt(AIR["gamma"] * 1e5 / AIR["rho"])
     scale = mach_rms * c_air / rms
     for v in vel:
-        v *= scale
-    p = np.full((n, n, n), 1e5)
+        v *= np.float32(scale)
+    p = 1e5
     w = _two_fluid_w(alpha_w, WATER["rho"], AIR["rho"], vel, p)
     if dtype != np.float64:
         w = w.astype(dtype)
