@@ -133,16 +133,42 @@ def adjoint_cost(n=256, steps=200, every=20):
             "adjoint_over_forward": round((tfb - tf) / tf, 3), "total_over_forward": round(tfb / tf, 3)}
 
 
-def roofline_of(kinds, neq, esize, ndim, ncell):
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_bubble_cloud_256.md")
+TRAFFIC_SOURCES = ("paper_2503_07953_amd/csrc/device.h", "paper_2503_07953_amd/csrc/sweep.hip")
+
+
+def measured_traffic_bytes(kind, prec, ncell):
+    """Calibrated HBM bytes per launch of a sweep pass from the committed
+    FETCH_SIZE / WRITE_SIZE summary, or None when that summary was taken on a
+    different kernel source (sha256 of the forward-kernel files) or size."""
+    import hashlib
+    try:
+        line = next(l for l in open(TRAFFIC_FILE) if "traffic-data:" in l)
+        data = json.loads(line.split("traffic-data:", 1)[1])
+    except (OSError, StopIteration, ValueError):
+        return None
+    h = hashlib.sha256()
+    for src in TRAFFIC_SOURCES:
+        with open(os.path.join(ROOT, src), "rb") as f:
+            h.update(f.read())
+    if h.hexdigest() != data.get("source_sha256") or data.get("cells") != ncell:
+        return None
+    return data.get("bytes_per_launch", {}).get(f"{kind}_{prec}")
+
+
+def roofline_of(kinds, neq, esize, ndim, ncell, prec=None):
     """Roofline of the kernel kind with the largest total time: algorithmic
     bytes per launch over its average launch duration (HIP events)."""
     dom = max((k for k in kinds if kinds[k][1] > 0), key=lambda k: kinds[k][0])
     avg_ms = kinds[dom][0] / kinds[dom][1]
     bpc = pass_bytes_per_cell(dom, neq, esize, ndim)
     achieved = bpc * ncell / (avg_ms * 1e-3) / 1e9
+    tb = measured_traffic_bytes(dom, prec, ncell) if prec else None
+    traffic = round(tb / (avg_ms * 1e-3) / 1e9, 1) if tb else None
     return {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "avg_launch_ms": round(avg_ms, 5),
-            "alg_bytes_per_cell": round(bpc, 2)}
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "avg_launch_ms": round(avg_ms, 5),
+            "alg_bytes_per_cell": round(bpc, 2),
+            "traffic_bytes_per_cell": round(tb / ncell, 1) if tb else None}
 
 
 def field_group_errors(a, b, nf, ndim):
@@ -183,7 +209,7 @@ def periodic_slab_leg(n=512, steps=100, warmup=2):
         ms, kinds = time_steps(S, q, steps, 0, c.cfl)
         g = ms / steps * 1e6 / (c.ncell * 3)
         out[prec] = {"ns_per_cell_stage": round(g, 5), "ms_per_step": round(ms / steps, 4),
-                     "roofline": roofline_of(kinds, c.neq, esize, 3, c.ncell)}
+                     "roofline": roofline_of(kinds, c.neq, esize, 3, c.ncell, prec)}
         finals[prec] = q.double().cpu().numpy()
         log(f"slab {prec}: {out[prec]}")
         del S, q
@@ -260,7 +286,7 @@ def main():
     log(f"fp64: {ms_step:.3f} ms/step, {grind:.4f} ns/cell/stage, kinds {kinds}")
 
     # dominant kernel roofline
-    roofline = roofline_of(kinds, neq, 8, case.ndim, ncell)
+    roofline = roofline_of(kinds, neq, 8, case.ndim, ncell, "fp64")
     dom, avg_ms = roofline["kernel"], roofline["avg_launch_ms"]
     flops_cell = FLOPS_PASS_3D2F + (FLOPS_STAGE_UPDATE if dom == "pass_z" else 0)
     tflops = flops_cell * ncell / (avg_ms * 1e-3) / 1e12
