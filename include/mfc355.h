@@ -28,6 +28,9 @@
  *   returns; the context owns only its own scratch.
  * Streams: every call is asynchronous on `hip_stream` (a hipStream_t; NULL
  *   is the default stream).  A context serves one stream at a time.
+ * Devices: a context belongs to the HIP device that was current at
+ *   mfc_create; every later call must be made with that device current
+ *   (MFC_ERR_ARG otherwise), and every array must live on it.
  * Errors: negative return codes.  Argument, shape and alignment checks run on
  *   the host before any HIP call.  Launch failures return MFC_ERR_HIP.  A
  *   face state with non-positive squared sound speed or a non-finite flux

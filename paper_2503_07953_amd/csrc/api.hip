@@ -124,7 +124,13 @@ int ensure_vjp_scratch(mfc_ctx* c) {
             hipMalloc((void**)&c->vbuf, state) == hipSuccess && hipMalloc((void**)&c->b1, state) == hipSuccess &&
             hipMalloc((void**)&c->b2, state) == hipSuccess;
   if (!ok) {
+    // release whatever was obtained, so that a later call retries from scratch
     (void)hipGetLastError();
+    void** bufs[] = {(void**)&c->vjp.G, (void**)&c->vjp.UF, (void**)&c->vbuf, (void**)&c->b1, (void**)&c->b2};
+    for (void** b : bufs) {
+      if (*b) (void)hipFree(*b);
+      *b = nullptr;
+    }
     c->err = "adjoint scratch allocation failed";
     return MFC_ERR_ALLOC;
   }
@@ -132,6 +138,15 @@ int ensure_vjp_scratch(mfc_ctx* c) {
 }
 
 bool aligned(const void* p, size_t a) { return (reinterpret_cast<uintptr_t>(p) % a) == 0; }
+
+int check_device(mfc_ctx* c) {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev != c->device) {
+    c->err = "the current HIP device is not the one the context was created on";
+    return MFC_ERR_ARG;
+  }
+  return MFC_OK;
+}
 
 int check_array(mfc_ctx* c, const void* p, const char* name) {
   if (!p) {
@@ -257,6 +272,10 @@ int mfc_create(const mfc_problem* p, mfc_ctx** out) {
 
 int mfc_destroy(mfc_ctx* c) {
   if (!c) return MFC_OK;
+  int prev = -1;
+  (void)hipGetDevice(&prev);
+  const int dev = c->device;
+  if (prev != dev) (void)hipSetDevice(dev);
   (void)hipDeviceSynchronize();
   if (c->acc) (void)hipFree(c->acc);
   if (c->q1) (void)hipFree(c->q1);
@@ -271,6 +290,7 @@ int mfc_destroy(mfc_ctx* c) {
   if (c->b2) (void)hipFree(c->b2);
   delete c->timer;
   delete c;
+  if (prev >= 0 && prev != dev) (void)hipSetDevice(prev);
   return MFC_OK;
 }
 
@@ -284,6 +304,7 @@ const char* mfc_last_error(const mfc_ctx* c) {
 
 int mfc_prim_to_cons(mfc_ctx* c, const void* w, void* q, void* stream) {
   if (!c) return MFC_ERR_ARG;
+  if (int rd = check_device(c)) return rd;
   int r;
   if ((r = check_array(c, w, "w")) || (r = check_array(c, q, "q"))) return r;
   if (w == q) return fail(c, MFC_ERR_ARG, "w and q alias");
@@ -296,6 +317,7 @@ int mfc_prim_to_cons(mfc_ctx* c, const void* w, void* q, void* stream) {
 
 int mfc_cons_to_prim(mfc_ctx* c, const void* q, void* w, void* stream) {
   if (!c) return MFC_ERR_ARG;
+  if (int rd = check_device(c)) return rd;
   int r;
   if ((r = check_array(c, w, "w")) || (r = check_array(c, q, "q"))) return r;
   if (w == q) return fail(c, MFC_ERR_ARG, "w and q alias");
@@ -308,6 +330,7 @@ int mfc_cons_to_prim(mfc_ctx* c, const void* q, void* w, void* stream) {
 
 int mfc_rhs(mfc_ctx* c, const void* q, void* rhs, void* stream) {
   if (!c) return MFC_ERR_ARG;
+  if (int rd = check_device(c)) return rd;
   int r;
   if ((r = check_array(c, q, "q")) || (r = check_array(c, rhs, "rhs"))) return r;
   if (q == rhs) return fail(c, MFC_ERR_ARG, "q and rhs alias");
@@ -324,6 +347,7 @@ int mfc_rhs(mfc_ctx* c, const void* q, void* rhs, void* stream) {
 
 int mfc_max_signal(mfc_ctx* c, const void* q, double* smax_dev, void* stream) {
   if (!c) return MFC_ERR_ARG;
+  if (int rd = check_device(c)) return rd;
   int r;
   if ((r = check_array(c, q, "q"))) return r;
   if (!smax_dev || !aligned(smax_dev, sizeof(double))) return fail(c, MFC_ERR_ARG, "bad smax pointer");
@@ -390,6 +414,7 @@ extern "C" {
 int mfc_step(mfc_ctx* c, void* q, double cfl, double dt_fixed, double t_remaining, double* dt_dev,
              void* stream) {
   if (!c) return MFC_ERR_ARG;
+  if (int rd = check_device(c)) return rd;
   int r;
   if ((r = check_array(c, q, "q"))) return r;
   if ((cfl > 0.0) == (dt_fixed > 0.0)) return fail(c, MFC_ERR_ARG, "exactly one of cfl and dt_fixed must be > 0");
@@ -404,6 +429,7 @@ int mfc_step(mfc_ctx* c, void* q, double cfl, double dt_fixed, double t_remainin
 
 int mfc_conserved_sums(mfc_ctx* c, const void* q, double* sums_dev, void* stream) {
   if (!c) return MFC_ERR_ARG;
+  if (int rd = check_device(c)) return rd;
   int r;
   if ((r = check_array(c, q, "q"))) return r;
   if (!sums_dev || !aligned(sums_dev, sizeof(double))) return fail(c, MFC_ERR_ARG, "bad sums pointer");
@@ -418,6 +444,7 @@ int mfc_conserved_sums(mfc_ctx* c, const void* q, double* sums_dev, void* stream
 
 int mfc_rhs_vjp(mfc_ctx* c, const void* q, const void* rhs_bar, void* q_bar, int accumulate, void* stream) {
   if (!c) return MFC_ERR_ARG;
+  if (int rd = check_device(c)) return rd;
   if (c->prob.precision != MFC_FP64) return fail(c, MFC_ERR_UNSUPPORTED, "adjoint entry points are FP64 only");
   int r;
   if ((r = check_array(c, q, "q")) || (r = check_array(c, rhs_bar, "rhs_bar")) || (r = check_array(c, q_bar, "q_bar")))
@@ -432,6 +459,7 @@ int mfc_rhs_vjp(mfc_ctx* c, const void* q, const void* rhs_bar, void* q_bar, int
 
 int mfc_step_vjp(mfc_ctx* c, const void* q_n, double dt, const void* qnp1_bar, void* qn_bar, void* stream) {
   if (!c) return MFC_ERR_ARG;
+  if (int rd = check_device(c)) return rd;
   if (c->prob.precision != MFC_FP64) return fail(c, MFC_ERR_UNSUPPORTED, "adjoint entry points are FP64 only");
   int r;
   if ((r = check_array(c, q_n, "q_n")) || (r = check_array(c, qnp1_bar, "qnp1_bar")) ||
@@ -457,6 +485,7 @@ int mfc_step_vjp(mfc_ctx* c, const void* q_n, double dt, const void* qnp1_bar, v
 
 int mfc_step_save_stages(mfc_ctx* c, void* q, double dt, void* q1, void* q2, void* stream) {
   if (!c) return MFC_ERR_ARG;
+  if (int rd = check_device(c)) return rd;
   if (c->prob.precision != MFC_FP64) return fail(c, MFC_ERR_UNSUPPORTED, "adjoint entry points are FP64 only");
   int r;
   if ((r = check_array(c, q, "q")) || (r = check_array(c, q1, "q1")) || (r = check_array(c, q2, "q2"))) return r;
@@ -481,6 +510,7 @@ int mfc_step_save_stages(mfc_ctx* c, void* q, double dt, void* q1, void* q2, voi
 int mfc_step_vjp_stages(mfc_ctx* c, const void* q_n, const void* q1, const void* q2, double dt,
                         const void* qnp1_bar, void* qn_bar, void* stream) {
   if (!c) return MFC_ERR_ARG;
+  if (int rd = check_device(c)) return rd;
   if (c->prob.precision != MFC_FP64) return fail(c, MFC_ERR_UNSUPPORTED, "adjoint entry points are FP64 only");
   int r;
   if ((r = check_array(c, q_n, "q_n")) || (r = check_array(c, q1, "q1")) || (r = check_array(c, q2, "q2")) ||
@@ -497,6 +527,7 @@ int mfc_step_vjp_stages(mfc_ctx* c, const void* q_n, const void* q1, const void*
 
 int mfc_cons_to_prim_vjp(mfc_ctx* c, const void* q, const void* w_bar, void* q_bar, int accumulate, void* stream) {
   if (!c) return MFC_ERR_ARG;
+  if (int rd = check_device(c)) return rd;
   if (c->prob.precision != MFC_FP64) return fail(c, MFC_ERR_UNSUPPORTED, "adjoint entry points are FP64 only");
   int r;
   if ((r = check_array(c, q, "q")) || (r = check_array(c, w_bar, "w_bar")) || (r = check_array(c, q_bar, "q_bar")))
@@ -509,6 +540,7 @@ int mfc_cons_to_prim_vjp(mfc_ctx* c, const void* q, const void* w_bar, void* q_b
 
 int mfc_prim_to_cons_vjp(mfc_ctx* c, const void* w, const void* q_bar, void* w_bar, int accumulate, void* stream) {
   if (!c) return MFC_ERR_ARG;
+  if (int rd = check_device(c)) return rd;
   if (c->prob.precision != MFC_FP64) return fail(c, MFC_ERR_UNSUPPORTED, "adjoint entry points are FP64 only");
   int r;
   if ((r = check_array(c, w, "w")) || (r = check_array(c, q_bar, "q_bar")) || (r = check_array(c, w_bar, "w_bar")))
@@ -521,6 +553,7 @@ int mfc_prim_to_cons_vjp(mfc_ctx* c, const void* w, const void* q_bar, void* w_b
 
 int mfc_set_timing(mfc_ctx* c, int enable) {
   if (!c) return MFC_ERR_ARG;
+  if (int rd = check_device(c)) return rd;
   if (enable && !c->timer) c->timer = new EventTimer();
   if (!enable && c->timer) {
     delete c->timer;
@@ -538,6 +571,7 @@ int mfc_get_timing(mfc_ctx* c, double* ms_sum, int64_t* counts) {
 
 int mfc_check(mfc_ctx* c, void* stream) {
   if (!c) return MFC_ERR_ARG;
+  if (int rd = check_device(c)) return rd;
   hipStream_t s = (hipStream_t)stream;
   hipError_t e = hipStreamSynchronize(s);
   if (e != hipSuccess) return hip_fail(c, e, "check: stream");
