@@ -46,6 +46,7 @@ class Solver:
         if rc != L.MFC_OK:
             raise L.MfcError(rc, "mfc_create")
         self.ctx = h
+        self._dev_index = self.device.index if self.device.index is not None else torch.cuda.current_device()
         self._scal = torch.zeros(4, dtype=torch.float64, device=self.device)
 
     @classmethod
@@ -70,7 +71,8 @@ class Solver:
     def _arr(self, t, name="q"):
         if not isinstance(t, torch.Tensor):
             raise TypeError(f"{name} must be a torch tensor")
-        if t.dtype != self.dtype or t.device.type != "cuda" or tuple(t.shape) != self.shape or not t.is_contiguous():
+        if (t.dtype != self.dtype or t.device.type != "cuda" or t.device.index != self._dev_index
+                or tuple(t.shape) != self.shape or not t.is_contiguous()):
             raise ValueError(f"{name}: expected contiguous {self.dtype} cuda tensor of shape {self.shape}, "
                              f"got {t.dtype} {t.device} {tuple(t.shape)}")
         return t
@@ -110,6 +112,8 @@ class Solver:
     def step(self, q, cfl=0.0, dt_fixed=0.0, t_remaining=0.0, dt_out=None):
         """Advance q in place by one SSP-RK3 step.  dt_out: optional device double tensor."""
         q = self._arr(q)
+        if dt_out is not None and (dt_out.dtype != torch.float64 or dt_out.device != q.device or dt_out.numel() < 1):
+            raise ValueError("dt_out must be a float64 tensor with at least one element on the solver's device")
         dp = ctypes.c_void_p(dt_out.data_ptr()) if dt_out is not None else ctypes.c_void_p()
         self._check(self.lib.mfc_step(self.ctx, _ptr(q), float(cfl), float(dt_fixed), float(t_remaining), dp,
                                       _stream()), "mfc_step")
