@@ -73,7 +73,8 @@ enum { MFC_FP64 = 0, MFC_FP32_MIXED = 1 };
 typedef struct {
   int32_t abi_version; /* must equal MFC_ABI_VERSION */
   int32_t ndim;        /* 1, 2 or 3 */
-  int32_t n[3];        /* interior cells per axis; >= 3 on active axes, 1 on unused */
+  int32_t n[3];        /* interior cells per axis; >= 3 on active axes, 1 on unused;
+                          n[1], n[2] <= 65535, n[0]*n[1]*n[2] <= 2^34 */
   int32_t num_fluids;  /* 1 (Euler) or 2 (five-equation model) */
   int32_t precision;   /* MFC_FP64 or MFC_FP32_MIXED */
   int32_t bc_lo[3];    /* MFC_BC_* per axis, low side */

@@ -223,9 +223,12 @@ int mfc_validate(const mfc_problem* p) {
     }
     ncell *= p->n[d];
   }
-  // grid launch limits: y and z extents index grid dimensions directly
-  if (p->n[1] > 65535 * 16 || p->n[2] > 65535 * 16) return MFC_ERR_SHAPE;
-  if (ncell > (1LL << 40)) return MFC_ERR_SHAPE;
+  // grid launch limits: the y and z extents index grid dimensions directly
+  // (gridDim.y and gridDim.z are at most 65535)
+  if (p->n[1] > 65535 || p->n[2] > 65535) return MFC_ERR_SHAPE;
+  // 2^34 cells already exceed the device memory of any state; it also keeps
+  // every one-dimensional grid (cells / 256 blocks) far inside its limit
+  if (ncell > (1LL << 34)) return MFC_ERR_SHAPE;
   for (int i = 0; i < p->num_fluids; ++i)
     if (!(p->gamma[i] > 1.0) || !(p->pi_inf[i] >= 0.0) || !(p->pi_inf[i] < 1e300)) return MFC_ERR_ARG;
   if (!(p->weno_eps > 0.0)) return MFC_ERR_ARG;

@@ -54,6 +54,12 @@ def test_num_eqs(L):
     (dict(precision=7), -3),
     (dict(n=(2, 8)), -2),
     (dict(n=(8, 8, 2)), -2),
+    (dict(n=(0, 8)), -2),
+    (dict(n=(-4, 8)), -2),
+    (dict(ndim=3, n=(8, 65536, 8), dx=(0.1,) * 3, bc_lo=(1,) * 3, bc_hi=(1,) * 3), -2),
+    (dict(ndim=3, n=(8, 8, 65536), dx=(0.1,) * 3, bc_lo=(1,) * 3, bc_hi=(1,) * 3), -2),
+    (dict(ndim=3, n=(1 << 21, 1 << 7, 1 << 7), dx=(0.1,) * 3, bc_lo=(1,) * 3, bc_hi=(1,) * 3), -2),
+    (dict(ndim=3, n=(1 << 20, 1 << 7, 1 << 7), dx=(0.1,) * 3, bc_lo=(1,) * 3, bc_hi=(1,) * 3), 0),
     (dict(dx=(0.0, 0.1)), -1),
     (dict(gamma=(1.0, 1.4)), -1),
     (dict(pi_inf=(-1.0, 0.0)), -1),
