@@ -136,8 +136,12 @@ int mfc_conserved_sums(mfc_ctx* ctx, const void* q, double* sums_dev, void* hip_
  * Hand-written reverse mode of the discrete operators above (not in the paper,
  * which has no adjoint): derivatives follow the branch the forward pass takes
  * (wave-speed min/max ties to the first argument, HLLC region order as in the
- * forward solver).  The first call allocates adjoint scratch in the context
- * (about 6*neq+1 doubles per face of the largest axis plus three states).
+ * forward solver).  The first call allocates adjoint scratch in the context:
+ * 6*neq+1 doubles per face of every axis when that sum is at most 8 GiB (all
+ * axes' face passes then run as one launch), else per face of the largest
+ * axis only, plus three states.  The environment variable
+ * MFC355_ADJOINT_FACE_BUDGET (bytes, read at that first call) overrides the
+ * 8 GiB threshold.
  * Outputs may not alias inputs.  accumulate != 0 adds to the output instead of
  * overwriting it. */
 

@@ -3,6 +3,7 @@
 // the right-hand side, the SSP-RK3 step and the diagnostics.
 #include <stdint.h>
 #include <stdio.h>
+#include <stdlib.h>
 #include <string.h>
 
 #include <string>
@@ -110,30 +111,54 @@ int hip_fail(mfc_ctx* c, hipError_t e, const char* where) {
   return MFC_ERR_HIP;
 }
 
+// Per-axis face buffers (all axes in one face launch) are used while their sum
+// stays within this many bytes; larger grids share one buffer across axes.
+constexpr size_t kAllAxesFaceBudget = size_t(8) << 30;
+
+void free_vjp_scratch(mfc_ctx* c) {
+  for (int d = 0; d < 3; ++d) {
+    if (c->vjp.Gd[d]) (void)hipFree(c->vjp.Gd[d]);
+    if (c->vjp.UFd[d]) (void)hipFree(c->vjp.UFd[d]);
+    c->vjp.Gd[d] = c->vjp.UFd[d] = nullptr;
+  }
+  void** bufs[] = {(void**)&c->vbuf, (void**)&c->b1, (void**)&c->b2};
+  for (void** b : bufs) {
+    if (*b) (void)hipFree(*b);
+    *b = nullptr;
+  }
+  c->vjp.all_axes = false;
+}
+
 int ensure_vjp_scratch(mfc_ctx* c) {
-  if (c->vjp.G) return MFC_OK;
-  long long maxfaces = 0;
+  if (c->vjp.Gd[0]) return MFC_OK;
+  long long faces[3] = {0, 0, 0}, maxfaces = 0, sumfaces = 0;
   for (int d = 0; d < c->prob.ndim; ++d) {
     const long long lines = c->ncell / c->prob.n[d];
-    const long long faces = lines * (c->prob.n[d] + 1);
-    if (faces > maxfaces) maxfaces = faces;
+    faces[d] = lines * (c->prob.n[d] + 1);
+    if (faces[d] > maxfaces) maxfaces = faces[d];
+    sumfaces += faces[d];
   }
+  const size_t per_face = (size_t)(6 * c->neq + 1) * sizeof(double);
+  size_t budget = kAllAxesFaceBudget;
+  if (const char* env = getenv("MFC355_ADJOINT_FACE_BUDGET")) budget = (size_t)strtoull(env, nullptr, 10);
+  const bool all_axes = (size_t)sumfaces * per_face <= budget;
   const size_t state = (size_t)c->neq * (size_t)c->ncell * sizeof(double);
-  bool ok = hipMalloc((void**)&c->vjp.G, (size_t)6 * c->neq * (size_t)maxfaces * sizeof(double)) == hipSuccess &&
-            hipMalloc((void**)&c->vjp.UF, (size_t)maxfaces * sizeof(double)) == hipSuccess &&
-            hipMalloc((void**)&c->vbuf, state) == hipSuccess && hipMalloc((void**)&c->b1, state) == hipSuccess &&
-            hipMalloc((void**)&c->b2, state) == hipSuccess;
+  bool ok = true;
+  for (int d = 0; d < (all_axes ? c->prob.ndim : 1) && ok; ++d) {
+    const long long nf = all_axes ? faces[d] : maxfaces;
+    ok = hipMalloc((void**)&c->vjp.Gd[d], (size_t)6 * c->neq * (size_t)nf * sizeof(double)) == hipSuccess &&
+         hipMalloc((void**)&c->vjp.UFd[d], (size_t)nf * sizeof(double)) == hipSuccess;
+  }
+  ok = ok && hipMalloc((void**)&c->vbuf, state) == hipSuccess && hipMalloc((void**)&c->b1, state) == hipSuccess &&
+       hipMalloc((void**)&c->b2, state) == hipSuccess;
   if (!ok) {
     // release whatever was obtained, so that a later call retries from scratch
     (void)hipGetLastError();
-    void** bufs[] = {(void**)&c->vjp.G, (void**)&c->vjp.UF, (void**)&c->vbuf, (void**)&c->b1, (void**)&c->b2};
-    for (void** b : bufs) {
-      if (*b) (void)hipFree(*b);
-      *b = nullptr;
-    }
+    free_vjp_scratch(c);
     c->err = "adjoint scratch allocation failed";
     return MFC_ERR_ALLOC;
   }
+  c->vjp.all_axes = all_axes;
   return MFC_OK;
 }
 
@@ -250,7 +275,7 @@ int mfc_create(const mfc_problem* p, mfc_ctx** out) {
   c->scal = c->partial = nullptr;
   c->flag = nullptr;
   c->timer = nullptr;
-  c->vjp = mfc::VjpScratch{nullptr, nullptr};
+  c->vjp = mfc::VjpScratch{{nullptr, nullptr, nullptr}, {nullptr, nullptr, nullptr}, false};
   c->vbuf = c->b1 = c->b2 = nullptr;
   if (hipGetDevice(&c->device) != hipSuccess) {
     delete c;
@@ -286,11 +311,7 @@ int mfc_destroy(mfc_ctx* c) {
   if (c->scal) (void)hipFree(c->scal);
   if (c->partial) (void)hipFree(c->partial);
   if (c->flag) (void)hipFree(c->flag);
-  if (c->vjp.G) (void)hipFree(c->vjp.G);
-  if (c->vjp.UF) (void)hipFree(c->vjp.UF);
-  if (c->vbuf) (void)hipFree(c->vbuf);
-  if (c->b1) (void)hipFree(c->b1);
-  if (c->b2) (void)hipFree(c->b2);
+  free_vjp_scratch(c);
   delete c->timer;
   delete c;
   if (prev >= 0 && prev != dev) (void)hipSetDevice(prev);

@@ -53,9 +53,13 @@ hipError_t launch_convert(int nf, int ndim, bool to_cons, const Params& pm, cons
 hipError_t launch_set_scalar(double* dst, double value, hipStream_t s);
 
 // Scratch of the adjoint passes (owned by the context, allocated on first use).
+// all_axes: one face buffer per axis (Gd[d], UFd[d]) so that the face passes of
+// every axis run in one launch; otherwise only Gd[0] / UFd[0] exist and the
+// axes are processed one after the other.
 struct VjpScratch {
-  double* G;          // per-face primitive cotangents of the 6 stencil positions
-  double* UF;         // per-face forward face velocity
+  double* Gd[3];    // per-face primitive cotangents of the 6 stencil positions
+  double* UFd[3];   // per-face forward face velocity
+  bool all_axes;
 };
 
 hipError_t launch_rhs_vjp(int nf, int ndim, const Params& pm, const double* q, const double* rbar, double* qbar,

@@ -359,3 +359,25 @@ def test_step_with_saved_stages_matches_step_and_step_vjp_bitwise():
     from paper_2503_07953_amd import _lib as L
     with pytest.raises(L.MfcError):
         S.step_save_stages(b, dt, q1, q1)
+
+
+@pytest.mark.parametrize("nd,n,nf,bc", [CASES[2], CASES[5]])
+def test_rhs_vjp_one_axis_at_a_time_matches_all_axes(nd, n, nf, bc, monkeypatch):
+    """The adjoint's two schedules: every axis's face pass in one launch with
+    one cell pass (default at these sizes), and one axis after the other through
+    a shared face buffer (forced by a zero face budget).  Same arithmetic per
+    face; only the order in which the axes' cotangents are summed differs."""
+    c = W.random_case(nd, n, nf=nf, seed=60 + nd, bc=bc, speed=200.0)
+    O = oracle.Oracle(c)
+    q = O.prim_to_cons(c.w)
+    lam = np.random.default_rng(3).normal(size=q.shape)
+    S_all = _solver(c)
+    g_all = S_all.rhs_vjp(S_all.to_device(q), S_all.to_device(lam)).cpu().numpy()
+    monkeypatch.setenv("MFC355_ADJOINT_FACE_BUDGET", "0")
+    S_seq = _solver(c)
+    g_seq = S_seq.rhs_vjp(S_seq.to_device(q), S_seq.to_device(lam)).cpu().numpy()
+    S_all.check()
+    S_seq.check()
+    err = field_errors(g_seq, g_all)
+    _say("sequential vs all-axes", err)
+    assert err.max() <= 1e-13
