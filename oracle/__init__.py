@@ -50,6 +50,7 @@ class OrcProblem(ctypes.Structure):
         ("gamma", ctypes.c_double * 2),
         ("pi_inf", ctypes.c_double * 2),
         ("weno_eps", ctypes.c_double),
+        ("weno_variant", ctypes.c_int32),
     ]
 
 
@@ -70,6 +71,8 @@ def lib():
             "orc_validate": (ctypes.c_int, [P]),
             "orc_weno5_js_left": (ctypes.c_double, [dp, ctypes.c_double]),
             "orc_weno5_js_right": (ctypes.c_double, [dp, ctypes.c_double]),
+            "orc_weno5_z_left": (ctypes.c_double, [dp, ctypes.c_double]),
+            "orc_weno5_z_right": (ctypes.c_double, [dp, ctypes.c_double]),
             "orc_hllc": (ctypes.c_int, [P, ctypes.c_int, dp, dp, dp, dp]),
             "orc_rhs": (ctypes.c_int, [P, dp, dp]),
             "orc_rhs_cells": (ctypes.c_int, [P, dp, ctypes.c_int64, i64p, dp]),
@@ -91,7 +94,7 @@ def lib():
     return _lib
 
 
-def problem(ndim, n, num_fluids, dx, gamma, pi_inf, bc_lo, bc_hi, weno_eps=1e-6) -> OrcProblem:
+def problem(ndim, n, num_fluids, dx, gamma, pi_inf, bc_lo, bc_hi, weno_eps=1e-6, weno_variant=0) -> OrcProblem:
     P = OrcProblem()
     P.ndim = ndim
     n = tuple(n) + (1,) * (3 - len(n))
@@ -105,6 +108,7 @@ def problem(ndim, n, num_fluids, dx, gamma, pi_inf, bc_lo, bc_hi, weno_eps=1e-6)
         P.gamma[i] = float(gamma[i]) if i < len(gamma) else float(gamma[0])
         P.pi_inf[i] = float(pi_inf[i]) if i < len(pi_inf) else float(pi_inf[0])
     P.weno_eps = weno_eps
+    P.weno_variant = int(weno_variant)
     return P
 
 
@@ -234,3 +238,14 @@ def weno5_js_left(f, eps=1e-6):
 def weno5_js_right(f, eps=1e-6):
     f = np.ascontiguousarray(f, dtype=np.float64)
     return lib().orc_weno5_js_right(_dp(f), eps)
+
+
+def weno5_z_left(f, eps=1e-6):
+    """Left-biased WENO5-Z value (Sec. 4.2.2) from f[0..4] = f_{i-2..i+2}."""
+    f = np.ascontiguousarray(f, dtype=np.float64)
+    return lib().orc_weno5_z_left(_dp(f), eps)
+
+
+def weno5_z_right(f, eps=1e-6):
+    f = np.ascontiguousarray(f, dtype=np.float64)
+    return lib().orc_weno5_z_right(_dp(f), eps)

@@ -44,6 +44,7 @@ typedef struct {
   double dx[3];
   double gamma[2], pi_inf[2];
   double weno_eps;
+  int32_t weno_variant; /* 0: WENO5-JS (Sec. 3.2.1), 1: WENO5-Z (Sec. 4.2.2) */
 } orc_problem;
 
 /* ------------------------------------------------------------------------ */
@@ -78,6 +79,7 @@ int orc_validate(const orc_problem* P) {
   for (int i = 0; i < P->num_fluids; ++i)
     if (!(P->gamma[i] > 1.0) || !(P->pi_inf[i] >= 0.0)) return ORC_ERR_ARG;
   if (!(P->weno_eps > 0)) return ORC_ERR_ARG;
+  if (P->weno_variant != 0 && P->weno_variant != 1) return ORC_ERR_ARG;
   return ORC_OK;
 }
 
@@ -220,6 +222,32 @@ double orc_weno5_js_right(const double* f, double eps) {
 }
 
 /* ------------------------------------------------------------------------ */
+/* WENO5-Z (Sec. 4.2.2, the Borges et al. weights as the paper prints them  */
+/* for order 2k-1 = 5): the same candidates and smoothness indicators as    */
+/* above, the global indicator tau = |beta_0 - beta_2|, and weights          */
+/* a_k = d_k (1 + (tau/(beta_k + eps))^q) with q = 1, normalized.            */
+/* ------------------------------------------------------------------------ */
+double orc_weno5_z_left(const double* f, double eps) {
+  double a = f[0], b = f[1], c = f[2], d = f[3], e = f[4];
+  double q0 = (2.0 * a - 7.0 * b + 11.0 * c) / 6.0;
+  double q1 = (-b + 5.0 * c + 2.0 * d) / 6.0;
+  double q2 = (2.0 * c + 5.0 * d - e) / 6.0;
+  double b0 = 13.0 / 12.0 * sq((a + c) - 2.0 * b) + 0.25 * sq((a + 3.0 * c) - 4.0 * b);
+  double b1 = 13.0 / 12.0 * sq((b + d) - 2.0 * c) + 0.25 * sq(b - d);
+  double b2 = 13.0 / 12.0 * sq((c + e) - 2.0 * d) + 0.25 * sq((3.0 * c + e) - 4.0 * d);
+  double tau = fabs(b0 - b2);
+  double a0 = 0.1 * (1.0 + tau / (b0 + eps));
+  double a1 = 0.6 * (1.0 + tau / (b1 + eps));
+  double a2 = 0.3 * (1.0 + tau / (b2 + eps));
+  return (a0 * q0 + a1 * q1 + a2 * q2) / (a0 + a1 + a2);
+}
+
+double orc_weno5_z_right(const double* f, double eps) {
+  double r[5] = {f[4], f[3], f[2], f[1], f[0]};
+  return orc_weno5_z_left(r, eps);
+}
+
+/* ------------------------------------------------------------------------ */
 /* HLLC face solver (Sec. 3.2.2; star states from Toro's book, the paper's  */
 /* reference for the solver).  Returns the flux of every row and the face   */
 /* velocity u_f that the non-conservative alpha term uses (Sec. 3.2.1: the  */
@@ -350,8 +378,13 @@ static int face_flux(const orc_problem* P, const double* q, int d, const int idx
       fl[s] = Wc[s][v];      /* centre m-1: cells m-3..m+1 */
       fr[s] = Wc[s + 1][v];  /* centre m:   cells m-2..m+2 */
     }
-    WL[v] = orc_weno5_js_left(fl, P->weno_eps);
-    WR[v] = orc_weno5_js_right(fr, P->weno_eps);
+    if (P->weno_variant == 1) {
+      WL[v] = orc_weno5_z_left(fl, P->weno_eps);
+      WR[v] = orc_weno5_z_right(fr, P->weno_eps);
+    } else {
+      WL[v] = orc_weno5_js_left(fl, P->weno_eps);
+      WR[v] = orc_weno5_js_right(fr, P->weno_eps);
+    }
   }
   return orc_hllc(P, d, WL, WR, F, uf);
 }

@@ -41,7 +41,7 @@ def sqrt(x):
 
 
 class Problem:
-    def __init__(self, ndim, n, num_fluids, dx, gamma, pi_inf, bc_lo, bc_hi, weno_eps=1e-6):
+    def __init__(self, ndim, n, num_fluids, dx, gamma, pi_inf, bc_lo, bc_hi, weno_eps=1e-6, weno_variant=0):
         self.ndim = ndim
         self.n = tuple(n) + (1,) * (3 - len(n))
         self.nf = num_fluids
@@ -51,6 +51,7 @@ class Problem:
         self.bc_lo = tuple(bc_lo) + (EXTRAP,) * (3 - len(bc_lo))
         self.bc_hi = tuple(bc_hi) + (EXTRAP,) * (3 - len(bc_hi))
         self.eps = weno_eps
+        self.weno_variant = int(weno_variant)
         self.neq = self.nf + ndim + 1 + (2 if self.nf == 2 else 0)
         self.G = [1.0 / (g - 1.0) for g in self.gamma]
         self.P = [g * p / (g - 1.0) for g, p in zip(self.gamma, self.pi_inf)]
@@ -168,6 +169,21 @@ def weno5_js_left(a, b, c, d, e, eps):
     return (a0 * q0 + a1 * q1 + a2 * q2) / (a0 + a1 + a2)
 
 
+def weno5_z_left(a, b, c, d, e, eps):
+    """WENO5-Z (Sec. 4.2.2): tau = |beta_0 - beta_2|, a_k = d_k (1 + tau/(beta_k + eps)), q = 1."""
+    q0 = (2.0 * a - 7.0 * b + 11.0 * c) / 6.0
+    q1 = (-b + 5.0 * c + 2.0 * d) / 6.0
+    q2 = (2.0 * c + 5.0 * d - e) / 6.0
+    b0 = 13.0 / 12.0 * ((a + c) - 2.0 * b) ** 2 + 0.25 * ((a + 3.0 * c) - 4.0 * b) ** 2
+    b1 = 13.0 / 12.0 * ((b + d) - 2.0 * c) ** 2 + 0.25 * (b - d) ** 2
+    b2 = 13.0 / 12.0 * ((c + e) - 2.0 * d) ** 2 + 0.25 * ((3.0 * c + e) - 4.0 * d) ** 2
+    tau = torch.abs(b0 - b2)
+    a0 = 0.1 * (1.0 + tau / (b0 + eps))
+    a1 = 0.6 * (1.0 + tau / (b1 + eps))
+    a2 = 0.3 * (1.0 + tau / (b2 + eps))
+    return (a0 * q0 + a1 * q1 + a2 * q2) / (a0 + a1 + a2)
+
+
 def _min_first(a, b):
     return torch.where(a <= b, a, b)
 
@@ -244,8 +260,9 @@ def axis_contribution(P: Problem, q, d):
     # faces m - 1/2, m = 0..n; padded index of cell g is g + 3
     fl = [_sl(wp, ax, s, n + 1) for s in range(5)]       # centre m-1: cells m-3..m+1
     fr = [_sl(wp, ax, s + 1, n + 1) for s in range(5)]   # centre m: cells m-2..m+2
-    WL = weno5_js_left(fl[0], fl[1], fl[2], fl[3], fl[4], P.eps)
-    WR = weno5_js_left(fr[4], fr[3], fr[2], fr[1], fr[0], P.eps)
+    weno = weno5_z_left if P.weno_variant == 1 else weno5_js_left
+    WL = weno(fl[0], fl[1], fl[2], fl[3], fl[4], P.eps)
+    WR = weno(fr[4], fr[3], fr[2], fr[1], fr[0], P.eps)
     F, uf, _ = hllc(P, d, WL, WR)
     inv_dx = 1.0 / P.dx[d]
     Flo, Fhi = _sl(F, ax, 0, n), _sl(F, ax, 1, n)

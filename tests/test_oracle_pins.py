@@ -163,6 +163,99 @@ def test_weno_nonoscillatory_at_step():
 
 
 # --------------------------------------------------------------------------
+# WENO5-Z (Sec. 4.2.2): tau = |beta_0 - beta_2|, a_k = d_k (1 + tau/(beta_k + eps)), q = 1
+# --------------------------------------------------------------------------
+def test_weno_z_constants_and_quadratics_exact():
+    # constants: tau = 0 leaves the weights at (0.1, 0.6, 0.3), whose binary sum
+    # is 1 only to rounding, so the value is the constant to within 2 ulp
+    for v in [0.375, -12.5, 1024.0]:
+        f = np.full(5, v)
+        assert abs(oracle.weno5_z_left(f) - v) <= 2 * ULP * abs(v)
+        assert abs(oracle.weno5_z_right(f) - v) <= 2 * ULP * abs(v)
+    rng = np.random.default_rng(11)
+    h = 0.1
+    for _ in range(5):
+        coef = rng.normal(size=3)
+        f = np.array([_avg_poly(coef, (k - 2.5) * h, (k - 1.5) * h) for k in range(5)])
+        exact_r = sum(ck * (0.5 * h) ** k for k, ck in enumerate(coef))
+        exact_l = sum(ck * (-0.5 * h) ** k for k, ck in enumerate(coef))
+        assert abs(oracle.weno5_z_left(f) - exact_r) <= 1e-13 * (1 + abs(exact_r))
+        assert abs(oracle.weno5_z_right(f) - exact_l) <= 1e-13 * (1 + abs(exact_l))
+
+
+def test_weno_z_symmetric_stencil_gives_the_linear_scheme():
+    """f = (a, b, c, b, a) makes beta_0 = beta_2, so tau = 0 and the Z weights
+    are exactly the linear weights, whatever the data and eps: the value is the
+    fifth-order upwind (2, -13, 47, 27, -3)/60 combination.  JS does not
+    reduce there (its weights follow beta_1 != beta_0)."""
+    rng = np.random.default_rng(12)
+    for _ in range(100):
+        a, b, c = rng.normal(size=3) * rng.choice([1e-3, 1.0, 1e3])
+        f = np.array([a, b, c, b, a])
+        lin = (2 * a - 13 * b + 47 * c + 27 * b - 3 * a) / 60.0
+        scale = np.abs(f).max()
+        assert abs(oracle.weno5_z_left(f) - lin) <= 16 * ULP * scale
+    f = np.array([0.0, 1.0, 0.0, 1.0, 0.0])
+    assert abs(oracle.weno5_z_left(f) - (-13 + 27) / 60.0) <= 4 * ULP
+    assert abs(oracle.weno5_js_left(f) - (-13 + 27) / 60.0) > 1e-3
+
+
+def test_weno_z_linear_limit_and_step():
+    rng = np.random.default_rng(13)
+    h = 0.05
+    for _ in range(5):
+        coef = rng.normal(size=5)
+        f = np.array([_avg_poly(coef, (k - 2.5) * h, (k - 1.5) * h) for k in range(5)])
+        lin = (2 * f[0] - 13 * f[1] + 47 * f[2] + 27 * f[3] - 3 * f[4]) / 60.0
+        assert abs(oracle.weno5_z_left(f, eps=1e30) - lin) <= 1e-13 * (1 + abs(lin))
+    v = oracle.weno5_z_left(np.array([0.0, 0.0, 0.0, 1.0, 1.0]))
+    assert 0.0 <= v < 1e-3
+    v = oracle.weno5_z_left(np.array([0.0, 0.0, 1.0, 1.0, 1.0]))
+    assert abs(v - 1.0) < 1e-3
+
+
+def test_weno_z_closer_to_the_linear_scheme_than_js_at_a_smooth_extremum():
+    """Around a smooth critical point the Z weights stay nearer the linear ones
+    (the reason the paper cites for the construction)."""
+    for h in (0.1, 0.05, 0.025):
+        xs = (np.arange(5) - 2) * h + 0.3 * h
+        f = np.array([(np.sin(x + h / 2) - np.sin(x - h / 2)) / h for x in xs]) + 2.0   # averages of cos
+        lin = (2 * f[0] - 13 * f[1] + 47 * f[2] + 27 * f[3] - 3 * f[4]) / 60.0
+        dz = abs(oracle.weno5_z_left(f, eps=1e-40) - lin)
+        dj = abs(oracle.weno5_js_left(f, eps=1e-40) - lin)
+        assert dz < dj, (h, dz, dj)
+
+
+def test_weno_z_exponent_is_one():
+    """With c = d = e the third stencil has beta_2 = 0, so tau = beta_0 and its
+    weight grows like (beta_0/eps)^q: the departure of the value from c then
+    shrinks like eps^q.  Tenfold smaller eps must give a tenfold smaller
+    departure (q = 1), not a hundredfold one (q = 2)."""
+    f = np.array([0.3, 0.7, 1.0, 1.0, 1.0])
+    d1 = oracle.weno5_z_left(f, eps=1e-6) - 1.0
+    d2 = oracle.weno5_z_left(f, eps=1e-7) - 1.0
+    assert 9.0 < d1 / d2 < 11.0, (d1, d2)
+
+
+def test_weno_z_fifth_order_advection_convergence():
+    """The paper's convergence problem (Sec. 3.5) with WENO-Z, which the paper
+    reports recovering its design order (Sec. 4.2.2)."""
+    errs = []
+    for N in (16, 32, 64):
+        c = W.advection_1d(N, amplitude=0.25, gamma2=1.6)
+        c.weno_variant = 1
+        O = oracle.Oracle(c)
+        q = O.prim_to_cons(c.w)
+        T, h = 5.0, 1.0 / N
+        ns = int(np.ceil(T / (0.25 * h ** (5.0 / 3.0))))
+        O.run(q, ns, dt_fixed=T / ns)
+        ex = W.advection_exact_average(N, 0.25, T)
+        errs.append(np.sqrt(np.mean((q[4, 0, 0] - ex) ** 2)))
+    orders = np.log2(np.array(errs[:-1]) / np.array(errs[1:]))
+    assert orders[-1] >= 4.5, orders
+
+
+# --------------------------------------------------------------------------
 # C-5: HLLC
 # --------------------------------------------------------------------------
 def _prim_state(rng, nf=2, D=3, speed=100.0):
@@ -360,7 +453,13 @@ def test_rhs_cells_matches_full_rhs_bitwise():
                                          (3, (12, 10, 9), 2, (1, 2, 0)), (1, (30,), 2, (2,))])
 def test_independent_torch_implementation_agrees_bitwise(nd, n, nf, bc):
     """The whole-array torch version (independent code) reproduces the oracle bit for bit."""
+    for variant in (0, 1):
+        _torch_agrees(nd, n, nf, bc, variant)
+
+
+def _torch_agrees(nd, n, nf, bc, variant):
     c = W.random_case(nd, n, nf=nf, seed=3, bc=bc)
+    c.weno_variant = variant
     O = oracle.Oracle(c)
     q = O.prim_to_cons(c.w)
     P = TR.Problem.from_case(c)
