@@ -230,6 +230,22 @@ def periodic_slab_leg(n=512, steps=100, warmup=2):
     return out
 
 
+def weno_z_grind(case, steps=20, warmup=3):
+    """The same bubble cloud with WENO5-Z weights (Sec. 4.2.2): FP64 and FP32 grind."""
+    import dataclasses
+
+    from paper_2503_07953_amd.solver import Solver
+    cz = dataclasses.replace(case, weno_variant=1)
+    out = {}
+    for prec in ("fp64", "fp32"):
+        S = Solver.from_case(cz, precision=prec)
+        q = S.prim_to_cons(S.to_device(cz.w))
+        ms, _ = time_steps(S, q, steps, warmup, cz.cfl, kernel_steps=0)
+        out[f"{prec}_ns_per_cell_stage"] = round(ms / steps * 1e6 / (cz.ncell * 3), 5)
+        del S, q
+    return out
+
+
 def shock_cylinder_grind(n=512, steps=100, warmup=5):
     import torch
 
@@ -323,7 +339,8 @@ def main():
         log(f"adjoint: {adj}")
     extra = None
     if not args.no_extra:
-        extra = {"shock_cylinder_512_fp64_ns_per_cell_stage": shock_cylinder_grind()}
+        extra = {"shock_cylinder_512_fp64_ns_per_cell_stage": shock_cylinder_grind(),
+                 "bubble_cloud_weno_z": weno_z_grind(case, args.steps, args.warmup)}
         log(f"extra: {extra}")
     slab = None
     if not args.no_slab:

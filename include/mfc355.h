@@ -46,7 +46,7 @@
 extern "C" {
 #endif
 
-#define MFC_ABI_VERSION 1
+#define MFC_ABI_VERSION 2
 
 enum {
   MFC_OK = 0,
@@ -70,6 +70,12 @@ enum { MFC_BC_PERIODIC = 0, MFC_BC_EXTRAP = 1, MFC_BC_SLIPWALL = 2 };
  * combination, the CFL reduction and the conservation sums. */
 enum { MFC_FP64 = 0, MFC_FP32_MIXED = 1 };
 
+/* Reconstruction weights: Jiang-Shu (Sec. 3.2.1) or the WENO-Z weights the
+ * paper prints for order 5, a_k = d_k (1 + tau/(beta_k + eps)) with
+ * tau = |beta_0 - beta_2| and exponent q = 1 (Sec. 4.2.2).  Both use the same
+ * candidates, smoothness indicators, linear weights and eps. */
+enum { MFC_WENO_JS = 0, MFC_WENO_Z = 1 };
+
 typedef struct {
   int32_t abi_version; /* must equal MFC_ABI_VERSION */
   int32_t ndim;        /* 1, 2 or 3 */
@@ -82,7 +88,8 @@ typedef struct {
   double dx[3];        /* uniform spacing per axis (> 0 on active axes) */
   double gamma[2];     /* stiffened-gas gamma_i > 1 per fluid (Sec. 2.2) */
   double pi_inf[2];    /* stiffened-gas pi_inf,i >= 0 per fluid */
-  double weno_eps;     /* WENO5-JS smoothness regularization, > 0 (1e-6) */
+  double weno_eps;     /* WENO smoothness regularization, > 0 (1e-6) */
+  int32_t weno_variant; /* MFC_WENO_JS or MFC_WENO_Z */
 } mfc_problem;
 
 typedef struct mfc_ctx mfc_ctx;

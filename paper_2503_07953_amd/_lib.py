@@ -13,7 +13,8 @@ import os
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libmfc355.so")
 
-MFC_ABI_VERSION = 1
+MFC_ABI_VERSION = 2
+MFC_WENO_JS, MFC_WENO_Z = 0, 1
 MFC_OK, MFC_ERR_ARG, MFC_ERR_SHAPE, MFC_ERR_UNSUPPORTED = 0, -1, -2, -3
 MFC_ERR_HIP, MFC_ERR_NONFINITE, MFC_ERR_ALLOC = -4, -5, -6
 MFC_BC_PERIODIC, MFC_BC_EXTRAP, MFC_BC_SLIPWALL = 0, 1, 2
@@ -33,6 +34,7 @@ class mfc_problem(ctypes.Structure):
         ("gamma", ctypes.c_double * 2),
         ("pi_inf", ctypes.c_double * 2),
         ("weno_eps", ctypes.c_double),
+        ("weno_variant", ctypes.c_int32),
     ]
 
 
@@ -108,7 +110,7 @@ class MfcError(RuntimeError):
 
 
 def make_problem(ndim, n, num_fluids, dx, gamma, pi_inf, bc_lo, bc_hi, weno_eps=1e-6,
-                 precision=MFC_FP64) -> mfc_problem:
+                 precision=MFC_FP64, weno_variant=MFC_WENO_JS) -> mfc_problem:
     p = mfc_problem()
     p.abi_version = MFC_ABI_VERSION
     p.ndim = int(ndim)
@@ -124,4 +126,5 @@ def make_problem(ndim, n, num_fluids, dx, gamma, pi_inf, bc_lo, bc_hi, weno_eps=
         p.gamma[i] = float(gamma[i] if i < len(gamma) else gamma[0])
         p.pi_inf[i] = float(pi_inf[i] if i < len(pi_inf) else pi_inf[0])
     p.weno_eps = float(weno_eps)
+    p.weno_variant = int(weno_variant)
     return p

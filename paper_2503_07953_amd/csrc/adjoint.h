@@ -141,6 +141,62 @@ __host__ __device__ __forceinline__ void weno_left_vjp(double a, double b, doubl
   g[4] += gD3;
 }
 
+// Adjoint of the left-biased WENO5-Z value (Sec. 4.2.2) in the same difference
+// form: with s_k = 4 (eps + beta_k) and tau = |s_0 - s_2|, the weights are
+// a_k = d_k (s_k + tau)/s_k and y = c + sum_k w_k l_k/6, w_k = a_k/A, A = sum a_k.
+// Cotangents: of a_k, G_k = gy (l_k/6 - (y - c))/A; of s_k through a_k,
+// -G_k d_k tau/s_k^2; of tau, sum_k G_k d_k/s_k, which reaches s_0 and s_2 with
+// the sign of s_0 - s_2 (none at a tie).  One refined reciprocal of
+// Z s_0 s_1 s_2 (Z = A s_0 s_1 s_2) gives 1/Z, 1/A and every 1/s_k.
+// Accumulates g[0..4].
+__host__ __device__ __forceinline__ void weno_z_left_vjp(double a, double b, double c, double d, double e,
+                                                         double eps, double gy, double* g) {
+  const double D0 = b - a, D1 = c - b, D2 = d - c, D3 = e - d;
+  const double u0 = D1 - D0, v0 = 3.0 * D1 - D0;
+  const double u1 = D2 - D1, v1 = D1 + D2;
+  const double u2 = D3 - D2, v2 = D3 - 3.0 * D2;
+  const double e4 = 4.0 * eps;
+  const double s0 = e4 + ((13.0 / 3.0) * u0 * u0 + v0 * v0);
+  const double s1 = e4 + ((13.0 / 3.0) * u1 * u1 + v1 * v1);
+  const double s2 = e4 + ((13.0 / 3.0) * u2 * u2 + v2 * v2);
+  const double tau = fabs(s0 - s2);
+  const double m0 = s1 * s2, m1 = s0 * s2, m2 = s0 * s1;   // prod_{j != k} s_j
+  const double P = s0 * m0;
+  const double z0 = 0.1 * ((s0 + tau) * m0), z1 = 0.6 * ((s1 + tau) * m1), z2 = 0.3 * ((s2 + tau) * m2);
+  const double Z = z0 + z1 + z2;
+  const double inv = fast_rcp(Z * P);
+  const double rZ = P * inv;    // 1/Z
+  const double rA = P * rZ;     // 1/A
+  const double rP = Z * inv;    // 1/(s0 s1 s2)
+  const double w0 = z0 * rZ, w1 = z1 * rZ, w2 = z2 * rZ;
+  const double l0 = 5.0 * D1 - 2.0 * D0, l1 = D1 + 2.0 * D2, l2 = 4.0 * D2 - D3;
+  const double k6 = 1.0 / 6.0;
+  const double dy = (w0 * l0 + w1 * l1 + w2 * l2) * k6;
+  // cotangents of l_k, of the weights a_k, of tau and of s_k
+  const double gk = gy * k6;
+  const double gl0 = gk * w0, gl1 = gk * w1, gl2 = gk * w2;
+  const double G0 = gy * (l0 * k6 - dy) * rA, G1 = gy * (l1 * k6 - dy) * rA, G2 = gy * (l2 * k6 - dy) * rA;
+  const double rs0 = m0 * rP, rs1 = m1 * rP, rs2 = m2 * rP;
+  const double gtau = 0.1 * G0 * rs0 + 0.6 * G1 * rs1 + 0.3 * G2 * rs2;
+  const double sg = (s0 > s2) ? 1.0 : ((s0 < s2) ? -1.0 : 0.0);
+  const double gs0 = -0.1 * G0 * tau * (rs0 * rs0) + sg * gtau;
+  const double gs1 = -0.6 * G1 * tau * (rs1 * rs1);
+  const double gs2 = -0.3 * G2 * tau * (rs2 * rs2) - sg * gtau;
+  const double gu0 = gs0 * (26.0 / 3.0) * u0, gv0 = gs0 * 2.0 * v0;
+  const double gu1 = gs1 * (26.0 / 3.0) * u1, gv1 = gs1 * 2.0 * v1;
+  const double gu2 = gs2 * (26.0 / 3.0) * u2, gv2 = gs2 * 2.0 * v2;
+  // back to the differences, then to the five values
+  const double gD0 = -2.0 * gl0 - gu0 - gv0;
+  const double gD1 = 5.0 * gl0 + gl1 + gu0 + 3.0 * gv0 - gu1 + gv1;
+  const double gD2 = 2.0 * gl1 + 4.0 * gl2 + gu1 + gv1 - gu2 - 3.0 * gv2;
+  const double gD3 = -gl2 + gu2 + gv2;
+  g[0] -= gD0;
+  g[1] += gD0 - gD1;
+  g[2] += gy + gD1 - gD2;
+  g[3] += gD2 - gD3;
+  g[4] += gD3;
+}
+
 // Adjoint of one reconstruction centre: gL is the cotangent of the left-biased
 // value at i+1/2, gR of the right-biased value at i-1/2 (the mirror image).
 __host__ __device__ __forceinline__ void weno5_js_vjp(const double* f, double eps, double gL, double gR, double* g) {

@@ -19,7 +19,7 @@ struct Params {
   int n[3];            // interior cells per axis (unused axes: 1)
   int bc_lo[3];        // BC kind per axis, low side
   int bc_hi[3];        // BC kind per axis, high side
-  int pad_;
+  int weno_z;          // 1: WENO5-Z weights (Sec. 4.2.2), 0: WENO5-JS
   double inv_dx[3];    // 1/dx per axis
   double G[2];         // 1/(gamma_i - 1)
   double P[2];         // gamma_i pi_inf,i/(gamma_i - 1)
@@ -193,6 +193,75 @@ __device__ __forceinline__ void weno5_js(float a, float b, float c, float d, flo
   const float wr0 = 0.1f * a2, wr2 = 0.3f * a0;
   fl = c + (wl0 * l0 + w1 * l1 + wl2 * l2) * __builtin_amdgcn_rcpf(6.0f * (wl0 + w1 + wl2));
   fr = c + (wr0 * r0 + w1 * r1 + wr2 * r2) * __builtin_amdgcn_rcpf(6.0f * (wr0 + w1 + wr2));
+}
+
+// WENO5-Z (Sec. 4.2.2): the same candidates and smoothness indicators, the
+// global indicator tau = |beta_0 - beta_2| and weights d_k (1 + tau/(beta_k +
+// eps)) (exponent q = 1).  With s_k = 4 (eps + beta_k) as above, tau' = |s_0 -
+// s_2| = 4 tau and the weights are d_k (s_k + tau')/s_k; over the common
+// denominator s_0 s_1 s_2 they become d_k (s_k + tau') prod_{j != k} s_j, so
+// both biased values again need one refined reciprocal.
+__host__ __device__ __forceinline__ void weno5_z(double a, double b, double c, double d, double e, double eps,
+                                                 double& fl, double& fr) {
+  const double D0 = b - a, D1 = c - b, D2 = d - c, D3 = e - d;
+  const double u0 = D1 - D0, v0 = 3.0 * D1 - D0;
+  const double u1 = D2 - D1, v1 = D1 + D2;
+  const double u2 = D3 - D2, v2 = D3 - 3.0 * D2;
+  const double e4 = 4.0 * eps;
+  const double s0 = e4 + ((13.0 / 3.0) * u0 * u0 + v0 * v0);
+  const double s1 = e4 + ((13.0 / 3.0) * u1 * u1 + v1 * v1);
+  const double s2 = e4 + ((13.0 / 3.0) * u2 * u2 + v2 * v2);
+  const double tau = fabs(s0 - s2);
+  const double z0 = (s0 + tau) * (s1 * s2), z1 = (s1 + tau) * (s0 * s2), z2 = (s2 + tau) * (s0 * s1);
+  const double l0 = 5.0 * D1 - 2.0 * D0, l1 = D1 + 2.0 * D2, l2 = 4.0 * D2 - D3;
+  const double r0 = 2.0 * D3 - 5.0 * D2, r1 = -(D2 + 2.0 * D1), r2 = D0 - 4.0 * D1;
+  const double w1 = 0.6 * z1;
+  const double wl0 = 0.1 * z0, wl2 = 0.3 * z2;
+  const double wr0 = 0.1 * z2, wr2 = 0.3 * z0;
+  const double nl = wl0 * l0 + w1 * l1 + wl2 * l2;
+  const double nr = wr0 * r0 + w1 * r1 + wr2 * r2;
+  const double dl = wl0 + w1 + wl2;
+  const double dr = wr0 + w1 + wr2;
+  const double inv = fast_rcp(6.0 * (dl * dr));
+  fl = c + nl * (dr * inv);
+  fr = c + nr * (dl * inv);
+}
+
+// FP32 WENO5-Z: products of s's would overflow float for pressure-sized data,
+// so each weight uses a hardware reciprocal of its s_k and each biased value
+// its own normalization.
+__device__ __forceinline__ void weno5_z(float a, float b, float c, float d, float e, float eps, float& fl,
+                                        float& fr) {
+  const float D0 = b - a, D1 = c - b, D2 = d - c, D3 = e - d;
+  const float u0 = D1 - D0, v0 = 3.0f * D1 - D0;
+  const float u1 = D2 - D1, v1 = D1 + D2;
+  const float u2 = D3 - D2, v2 = D3 - 3.0f * D2;
+  const float e4 = 4.0f * eps;
+  const float s0 = e4 + ((13.0f / 3.0f) * u0 * u0 + v0 * v0);
+  const float s1 = e4 + ((13.0f / 3.0f) * u1 * u1 + v1 * v1);
+  const float s2 = e4 + ((13.0f / 3.0f) * u2 * u2 + v2 * v2);
+  const float tau = fabsf(s0 - s2);
+  const float g0 = 1.0f + tau * __builtin_amdgcn_rcpf(s0);
+  const float g1 = 1.0f + tau * __builtin_amdgcn_rcpf(s1);
+  const float g2 = 1.0f + tau * __builtin_amdgcn_rcpf(s2);
+  const float l0 = 5.0f * D1 - 2.0f * D0, l1 = D1 + 2.0f * D2, l2 = 4.0f * D2 - D3;
+  const float r0 = 2.0f * D3 - 5.0f * D2, r1 = -(D2 + 2.0f * D1), r2 = D0 - 4.0f * D1;
+  const float w1 = 0.6f * g1;
+  const float wl0 = 0.1f * g0, wl2 = 0.3f * g2;
+  const float wr0 = 0.1f * g2, wr2 = 0.3f * g0;
+  fl = c + (wl0 * l0 + w1 * l1 + wl2 * l2) * __builtin_amdgcn_rcpf(6.0f * (wl0 + w1 + wl2));
+  fr = c + (wr0 * r0 + w1 * r1 + wr2 * r2) * __builtin_amdgcn_rcpf(6.0f * (wr0 + w1 + wr2));
+}
+
+// The reconstruction of a kernel instantiation: WZ selects WENO5-Z, else JS.
+// (A compile-time choice: a run-time branch inside the unrolled row loops
+// would make every kernel hold the registers of both.)
+template <bool WZ, typename T>
+__device__ __forceinline__ void weno5(T a, T b, T c, T d, T e, T eps, T& fl, T& fr) {
+  if constexpr (WZ)
+    weno5_z(a, b, c, d, e, eps, fl, fr);
+  else
+    weno5_js(a, b, c, d, e, eps, fl, fr);
 }
 
 // ---------------------------------------------------------------------------

@@ -66,6 +66,8 @@ def test_num_eqs(L):
     (dict(bc_lo=(0, 1), bc_hi=(1, 1)), -1),
     (dict(bc_lo=(5, 1)), -1),
     (dict(weno_eps=0.0), -1),
+    (dict(weno_variant=1), 0),
+    (dict(weno_variant=2), -3),
 ])
 def test_validation_codes(L, kw, code):
     lib = L.load()

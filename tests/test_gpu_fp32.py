@@ -26,7 +26,7 @@ def _say(*a):
     print("[gpu-fp32]", *a, flush=True)
 
 
-@pytest.mark.parametrize("kind", ["bubbles", "random"])
+@pytest.mark.parametrize("kind", ["bubbles", "random", "random-weno-z"])
 def test_fp32_form_within_float_envelope(kind):
     from paper_2503_07953_amd.solver import Solver
     if kind == "bubbles":
@@ -35,6 +35,7 @@ def test_fp32_form_within_float_envelope(kind):
     else:
         c = W.random_case(3, (40, 36, 30), nf=2, seed=5, bc=(W.EXTRAP, W.SLIPWALL, W.PERIODIC), speed=100.0)
         nsteps = 10
+        c.weno_variant = 1 if kind.endswith("weno-z") else 0
     O = oracle.Oracle(c)
     q = O.prim_to_cons(c.w)
     dts = O.run(q, nsteps, cfl=0.5)

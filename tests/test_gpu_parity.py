@@ -114,6 +114,43 @@ def test_cfl_steps_match_oracle(nd, n, nf, bc, nsteps):
     assert err.max() <= TOL, err
 
 
+@pytest.mark.parametrize("nd,n,nf,bc", [CASES[0], CASES[3], CASES[6], CASES[7]])
+def test_weno_z_rhs_and_steps_match_oracle(nd, n, nf, bc):
+    """The WENO5-Z reconstruction (Sec. 4.2.2) through the same kernels."""
+    _say("weno-z", nd, n, nf, bc)
+    c = W.random_case(nd, n, nf=nf, seed=500 + nd, bc=bc, speed=400.0 if nf == 1 else 150.0)
+    c.weno_variant = 1
+    O = oracle.Oracle(c)
+    q = O.prim_to_cons(c.w)
+    S = _solver(c)
+    qd = S.to_device(q)
+    err = conservative_errors(S.rhs(qd).cpu().numpy(), O.rhs(q), nf, nd)
+    assert err.max() <= TOL, err
+    dts = O.run(q, 5, cfl=0.5)
+    dt = torch.zeros(1, dtype=torch.float64, device="cuda")
+    gdts = []
+    for _ in range(5):
+        S.step(qd, cfl=0.5, dt_out=dt)
+        gdts.append(dt.item())
+    S.check()
+    assert np.allclose(gdts, dts, rtol=1e-13, atol=0)
+    err = conservative_errors(qd.cpu().numpy(), q, nf, nd)
+    assert err.max() <= TOL, err
+
+
+def test_weno_z_differs_from_js():
+    """The two reconstructions are distinct code paths (a non-smooth state)."""
+    c = W.random_case(2, (40, 30), nf=2, seed=9, bc=(W.EXTRAP, W.PERIODIC))
+    O = oracle.Oracle(c)
+    q = O.prim_to_cons(c.w)
+    S0 = _solver(c)
+    r0 = S0.rhs(S0.to_device(q)).cpu().numpy()
+    c.weno_variant = 1
+    S1 = _solver(c)
+    r1 = S1.rhs(S1.to_device(q)).cpu().numpy()
+    assert not np.array_equal(r0, r1)
+
+
 def test_sod_full_run_matches_oracle_and_exact():
     from oracle import exact_riemann as er
     c = W.sod(200)
