@@ -84,12 +84,16 @@ def load() -> ctypes.CDLL:
     if not os.path.exists(LIB_PATH):
         raise LibraryMissing(f"{LIB_PATH} is not built; run __graft_entry__.build() first")
     L = ctypes.CDLL(LIB_PATH)
+    missing = [name for name in SIGNATURES if not hasattr(L, name)]
+    if missing:
+        raise LibraryMissing(f"{LIB_PATH} lacks {', '.join(missing)}; rebuild it with __graft_entry__.build()")
     for name, (res, args) in SIGNATURES.items():
-        f = getattr(L, name, None)
-        if f is None:
-            continue
+        f = getattr(L, name)
         f.restype = res
         f.argtypes = args
+    if L.mfc_abi_version() != MFC_ABI_VERSION:
+        raise LibraryMissing(f"{LIB_PATH} has ABI version {L.mfc_abi_version()}, the binding expects "
+                             f"{MFC_ABI_VERSION}; rebuild it with __graft_entry__.build()")
     _lib = L
     return L
 

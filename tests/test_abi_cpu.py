@@ -94,3 +94,15 @@ def test_null_context_and_status_strings(L):
     for c in (0, -1, -2, -3, -4, -5, -6):
         assert L.status_string(c)
     assert lib.mfc_abi_version() == L.MFC_ABI_VERSION
+
+
+def test_missing_library_fails_loudly(tmp_path, monkeypatch):
+    """No CPU fallback: without the HIP library every entry raises."""
+    from paper_2503_07953_amd import _lib
+    monkeypatch.setattr(_lib, "_lib", None)
+    monkeypatch.setattr(_lib, "LIB_PATH", str(tmp_path / "libmfc355.so"))
+    with pytest.raises(_lib.LibraryMissing):
+        _lib.load()
+    from paper_2503_07953_amd.solver import Solver
+    with pytest.raises(_lib.LibraryMissing):
+        Solver(1, (8,), 1, (0.1,), (1.4, 1.4), (0.0, 0.0), (1,), (1,))
