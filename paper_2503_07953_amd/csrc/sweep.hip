@@ -27,21 +27,23 @@
 
 namespace mfc {
 
-template <int DIR, int D>
+template <int DIR, int D, typename Real>
 struct Tile {
   // TA: reconstruction centres per tile along the sweep axis (outputs TA - 2)
-  // TB: independent lines across the sweep axis
+  // TB: independent lines across the sweep axis (x lanes for y and z).  The
+  // FP64 middle (y) pass of a 3D stage runs 16 lanes (256-thread blocks, twice
+  // the blocks per CU); measured faster there, slower for z and for FP32.
   static constexpr int TA = (DIR == 0) ? 64 : 16;
-  static constexpr int TB = (DIR == 0) ? ((D == 1) ? 1 : 4) : 32;
+  static constexpr int TB = (DIR == 0) ? ((D == 1) ? 1 : 4) : ((DIR == 1 && D == 3 && sizeof(Real) == 8) ? 16 : 32);
   static constexpr int NT = TA * TB;
   static constexpr int OUT = TA - 2;
   static constexpr int SA = TA + 4;  // LDS slots along the sweep axis
 };
 
 // LDS index of (row v, slot s along the sweep axis, line b).
-template <int DIR, int D>
+template <int DIR, int D, typename Real>
 __device__ __forceinline__ int lds_index(int v, int s, int b) {
-  using TL = Tile<DIR, D>;
+  using TL = Tile<DIR, D, Real>;
   if constexpr (DIR == 0)
     return (v * TL::TB + b) * TL::SA + s;
   else
@@ -49,13 +51,13 @@ __device__ __forceinline__ int lds_index(int v, int s, int b) {
 }
 
 template <int NF, int D, int DIR, typename Real, int MODE, bool WZ>
-__global__ __launch_bounds__((Tile<DIR, D>::NT)) void sweep_kernel(Params pm, const Real* __restrict__ qk,
+__global__ __launch_bounds__((Tile<DIR, D, Real>::NT)) void sweep_kernel(Params pm, const Real* __restrict__ qk,
                                                                  Real* __restrict__ acc,
                                                                  const Real* __restrict__ qn,
                                                                  Real* __restrict__ qout, StageArgs st,
                                                                  int* __restrict__ flag) {
   using R = Rows<NF, D>;
-  using TL = Tile<DIR, D>;
+  using TL = Tile<DIR, D, Real>;
   constexpr int NEQ = R::NEQ;
   __shared__ Real sh[(NEQ + 1) * TL::SA * TL::TB];
 
@@ -119,7 +121,7 @@ __global__ __launch_bounds__((Tile<DIR, D>::NT)) void sweep_kernel(Params pm, co
     if (flip) U[R::MOM + DIR] = -U[R::MOM + DIR];
     cons_to_prim<NF, D>(pm, U, W);
 #pragma unroll
-    for (int v = 0; v < NEQ; ++v) sh[lds_index<DIR, D>(v, s, bb)] = Real(W[v]);
+    for (int v = 0; v < NEQ; ++v) sh[lds_index<DIR, D, Real>(v, s, bb)] = Real(W[v]);
   }
   __syncthreads();
 
@@ -143,22 +145,22 @@ __global__ __launch_bounds__((Tile<DIR, D>::NT)) void sweep_kernel(Params pm, co
     const Real eps = Real(pm.eps);
 #pragma unroll
     for (int v = 0; v < NEQ; ++v) {
-      const Real f0 = sh[lds_index<DIR, D>(v, a + 0, b)];
-      const Real f1 = sh[lds_index<DIR, D>(v, a + 1, b)];
-      const Real f2 = sh[lds_index<DIR, D>(v, a + 2, b)];
-      const Real f3 = sh[lds_index<DIR, D>(v, a + 3, b)];
-      const Real f4 = sh[lds_index<DIR, D>(v, a + 4, b)];
+      const Real f0 = sh[lds_index<DIR, D, Real>(v, a + 0, b)];
+      const Real f1 = sh[lds_index<DIR, D, Real>(v, a + 1, b)];
+      const Real f2 = sh[lds_index<DIR, D, Real>(v, a + 2, b)];
+      const Real f3 = sh[lds_index<DIR, D, Real>(v, a + 3, b)];
+      const Real f4 = sh[lds_index<DIR, D, Real>(v, a + 4, b)];
       weno5<WZ>(f0, f1, f2, f3, f4, eps, WLc[v], WRc[v]);
     }
     if constexpr (NF == 2) {
-      alpha_cell[0] = sh[lds_index<DIR, D>(R::ALPHA, a + 2, b)];
-      alpha_cell[1] = sh[lds_index<DIR, D>(R::ALPHA + 1, a + 2, b)];
+      alpha_cell[0] = sh[lds_index<DIR, D, Real>(R::ALPHA, a + 2, b)];
+      alpha_cell[1] = sh[lds_index<DIR, D, Real>(R::ALPHA + 1, a + 2, b)];
     }
   }
   __syncthreads();
   if (centre_ok) {
 #pragma unroll
-    for (int v = 0; v < NEQ; ++v) sh[lds_index<DIR, D>(v, a, b)] = WLc[v];
+    for (int v = 0; v < NEQ; ++v) sh[lds_index<DIR, D, Real>(v, a, b)] = WLc[v];
   }
   __syncthreads();
 
@@ -169,15 +171,15 @@ __global__ __launch_bounds__((Tile<DIR, D>::NT)) void sweep_kernel(Params pm, co
   if (face_ok) {
     Real WL[NEQ];
 #pragma unroll
-    for (int v = 0; v < NEQ; ++v) WL[v] = sh[lds_index<DIR, D>(v, a - 1, b)];
+    for (int v = 0; v < NEQ; ++v) WL[v] = sh[lds_index<DIR, D, Real>(v, a - 1, b)];
     const bool bad = hllc<NF, D, DIR, Real>(pm, WL, WRc, F, uf);
     if (bad) atomicOr(flag, 1);
   }
   __syncthreads();
   if (face_ok) {
 #pragma unroll
-    for (int v = 0; v < NEQ; ++v) sh[lds_index<DIR, D>(v, a, b)] = F[v];
-    sh[lds_index<DIR, D>(NEQ, a, b)] = uf;
+    for (int v = 0; v < NEQ; ++v) sh[lds_index<DIR, D, Real>(v, a, b)] = F[v];
+    sh[lds_index<DIR, D, Real>(NEQ, a, b)] = uf;
   }
   __syncthreads();
 
@@ -188,11 +190,11 @@ __global__ __launch_bounds__((Tile<DIR, D>::NT)) void sweep_kernel(Params pm, co
   else oz = c;
   const long long cell = ((long long)oz * ny + oy) * nx + ox;
   const Real inv_dx = Real(pm.inv_dx[DIR]);
-  const Real uhi = sh[lds_index<DIR, D>(NEQ, a + 1, b)];
+  const Real uhi = sh[lds_index<DIR, D, Real>(NEQ, a + 1, b)];
   const Real div = inv_dx * (uhi - uf);
 #pragma unroll
   for (int v = 0; v < NEQ; ++v) {
-    Real Dv = inv_dx * (F[v] - sh[lds_index<DIR, D>(v, a + 1, b)]);
+    Real Dv = inv_dx * (F[v] - sh[lds_index<DIR, D, Real>(v, a + 1, b)]);
     if constexpr (NF == 2) {
       if (v == R::ALPHA) Dv = Dv + alpha_cell[0] * div;
       if (v == R::ALPHA + 1) Dv = Dv + alpha_cell[1] * div;
@@ -224,7 +226,7 @@ __global__ __launch_bounds__((Tile<DIR, D>::NT)) void sweep_kernel(Params pm, co
 template <int NF, int D, int DIR, typename Real, int MODE, bool WZ>
 static hipError_t launch_one(const Params& pm, const Real* qk, Real* acc, const Real* qn, Real* qout,
                              StageArgs st, int* flag, hipStream_t s, PassTimer* tm) {
-  using TL = Tile<DIR, D>;
+  using TL = Tile<DIR, D, Real>;
   dim3 block, grid;
   const int nx = pm.n[0], ny = pm.n[1], nz = pm.n[2];
   if constexpr (DIR == 0) {
