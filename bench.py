@@ -58,24 +58,29 @@ FLOPS_PASS_3D2F = 21 + 97 * 8 + 106 + 30
 FLOPS_STAGE_UPDATE = 32
 
 
-def time_steps(S, q, steps, warmup, cfl, kernel_steps=None):
+def time_steps(S, q, steps, warmup, cfl, kernel_steps=None, repeats=1):
     """Wall time of `steps` CFL steps (HIP events on the stream, no per-launch
-    instrumentation), then per-kernel durations from the library's launch
-    events over `kernel_steps` further steps (default: `steps`), in a loop of
-    its own so that the event records do not inflate the step time."""
+    instrumentation), as the median of `repeats` back-to-back loops, then
+    per-kernel durations from the library's launch events over `kernel_steps`
+    further steps (default: `steps`), in a loop of their own so that the
+    event records do not inflate the step time.  Returns (median ms, kinds,
+    every repeat's ms)."""
     import torch
     for _ in range(warmup):
         S.step(q, cfl=cfl)
     torch.cuda.synchronize()
     stream = torch.cuda.current_stream()
-    t0 = torch.cuda.Event(enable_timing=True)
-    t1 = torch.cuda.Event(enable_timing=True)
-    t0.record(stream)
-    for _ in range(steps):
-        S.step(q, cfl=cfl)
-    t1.record(stream)
-    torch.cuda.synchronize()
-    ms = t0.elapsed_time(t1)
+    reps = []
+    for _ in range(repeats):
+        t0 = torch.cuda.Event(enable_timing=True)
+        t1 = torch.cuda.Event(enable_timing=True)
+        t0.record(stream)
+        for _ in range(steps):
+            S.step(q, cfl=cfl)
+        t1.record(stream)
+        torch.cuda.synchronize()
+        reps.append(t0.elapsed_time(t1))
+    ms = sorted(reps)[len(reps) // 2]
     S.set_timing(True)
     S.get_timing()
     for _ in range(steps if kernel_steps is None else kernel_steps):
@@ -84,7 +89,7 @@ def time_steps(S, q, steps, warmup, cfl, kernel_steps=None):
     kinds = S.get_timing()
     S.set_timing(False)
     S.check()
-    return ms, kinds
+    return ms, kinds, reps
 
 
 def adjoint_cost(n=256, steps=200, every=20):
@@ -213,7 +218,7 @@ def periodic_slab_leg(n=512, steps=100, warmup=2):
             S.step(q, cfl=c.cfl)
         q.copy_(q0)
         del q0
-        ms, kinds = time_steps(S, q, steps, 0, c.cfl, kernel_steps=10)
+        ms, kinds, _ = time_steps(S, q, steps, 0, c.cfl, kernel_steps=10)
         g = ms / steps * 1e6 / (c.ncell * 3)
         out[prec] = {"ns_per_cell_stage": round(g, 5), "ms_per_step": round(ms / steps, 4),
                      "roofline": roofline_of(kinds, c.neq, esize, 3, c.ncell, prec)}
@@ -240,7 +245,7 @@ def weno_z_grind(case, steps=20, warmup=3):
     for prec in ("fp64", "fp32"):
         S = Solver.from_case(cz, precision=prec)
         q = S.prim_to_cons(S.to_device(cz.w))
-        ms, _ = time_steps(S, q, steps, warmup, cz.cfl, kernel_steps=0)
+        ms, _, _ = time_steps(S, q, steps, warmup, cz.cfl, kernel_steps=0, repeats=3)
         out[f"{prec}_ns_per_cell_stage"] = round(ms / steps * 1e6 / (cz.ncell * 3), 5)
         del S, q
     return out
@@ -254,7 +259,7 @@ def shock_cylinder_grind(n=512, steps=100, warmup=5):
     c = W.shock_cylinder(n)
     S = Solver.from_case(c, precision="fp64")
     q = S.prim_to_cons(S.to_device(c.w))
-    ms, _ = time_steps(S, q, steps, warmup, c.cfl, kernel_steps=0)
+    ms, _, _ = time_steps(S, q, steps, warmup, c.cfl, kernel_steps=0, repeats=3)
     return round(ms / steps * 1e6 / (c.ncell * 3), 5)
 
 
@@ -263,6 +268,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--repeats", type=int, default=1,
+                    help="timed loops of --steps steps; the median is reported (default: exactly one loop)")
     ap.add_argument("--n", type=int, default=256, help="bubble-cloud grid edge (256 = the configuration)")
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -303,7 +310,7 @@ def main():
     # ---------------- FP64 ----------------
     S = Solver.from_case(case, precision="fp64")
     q = S.prim_to_cons(S.to_device(case.w))
-    ms, kinds = time_steps(S, q, args.steps, args.warmup, cfl)
+    ms, kinds, reps = time_steps(S, q, args.steps, args.warmup, cfl, repeats=args.repeats)
     ms_step = ms / args.steps
     grind = ms_step * 1e6 / (ncell * 3)
     log(f"fp64: {ms_step:.3f} ms/step, {grind:.4f} ns/cell/stage, kinds {kinds}")
@@ -322,11 +329,11 @@ def main():
     if not args.no_fp32:
         S32 = Solver.from_case(case, precision="fp32")
         q32 = S32.prim_to_cons(S32.to_device(case.w))
-        ms32, kinds32 = time_steps(S32, q32, args.steps, args.warmup, cfl)
+        ms32, kinds32, _ = time_steps(S32, q32, args.steps, args.warmup, cfl, repeats=args.repeats)
         g32 = ms32 / args.steps * 1e6 / (ncell * 3)
         linf, l2 = field_group_errors(q32.double().cpu().numpy(), q.cpu().numpy(), 2, 3)
         fp32 = {"ns_per_cell_stage": round(g32, 5), "speedup_vs_fp64": round(grind / g32, 3),
-                "steps_compared": args.warmup + 2 * args.steps,
+                "steps_compared": args.warmup + (args.repeats + 1) * args.steps,
                 "fields": ["alpha1 rho1", "alpha2 rho2", "momentum", "rho E", "alpha1", "alpha2"],
                 "error_vs_fp64_linf": linf, "error_vs_fp64_l2": l2}
         log(f"fp32: {g32:.4f} ns/cell/stage, speedup {grind / g32:.2f}, linf {linf}")
@@ -371,6 +378,9 @@ def main():
         "config": {"workload": f"3D air-water bubble cloud {args.n}^3, 64 bubbles, 100 bar pulse, "
                                f"2 fluids / 8 rows, WENO5-JS+HLLC+SSP-RK3, CFL 0.5",
                    "cells": ncell, "rows": neq},
+        "repeats": args.repeats,
+        "value_min_max": [round(min(reps) / args.steps * 1e6 / (ncell * 3), 5),
+                          round(max(reps) / args.steps * 1e6 / (ncell * 3), 5)],
         "grind_ns_per_cell_pde_rhs": round(grind / neq, 6),
         "hbm_frac_stage_alg": round(stage_bytes / (grind * 1e-9) / 1e9 / HBM_PEAK_GBS, 4),
         "kernel_ms": {k: [round(v[0], 4), v[1]] for k, v in kinds.items()},
