@@ -73,6 +73,8 @@ def lib():
             "orc_weno5_js_right": (ctypes.c_double, [dp, ctypes.c_double]),
             "orc_weno5_z_left": (ctypes.c_double, [dp, ctypes.c_double]),
             "orc_weno5_z_right": (ctypes.c_double, [dp, ctypes.c_double]),
+            "orc_teno5_left": (ctypes.c_double, [dp, ctypes.c_double, ctypes.c_double]),
+            "orc_teno5_right": (ctypes.c_double, [dp, ctypes.c_double, ctypes.c_double]),
             "orc_hllc": (ctypes.c_int, [P, ctypes.c_int, dp, dp, dp, dp]),
             "orc_rhs": (ctypes.c_int, [P, dp, dp]),
             "orc_rhs_cells": (ctypes.c_int, [P, dp, ctypes.c_int64, i64p, dp]),
@@ -249,3 +251,17 @@ def weno5_z_left(f, eps=1e-6):
 def weno5_z_right(f, eps=1e-6):
     f = np.ascontiguousarray(f, dtype=np.float64)
     return lib().orc_weno5_z_right(_dp(f), eps)
+
+
+TENO_CT = 1e-5
+
+
+def teno5_left(f, eps=1e-6, ct=TENO_CT):
+    """Left-biased TENO5 value (Sec. 4.2.2) from f[0..4] = f_{i-2..i+2}."""
+    f = np.ascontiguousarray(f, dtype=np.float64)
+    return lib().orc_teno5_left(_dp(f), eps, ct)
+
+
+def teno5_right(f, eps=1e-6, ct=TENO_CT):
+    f = np.ascontiguousarray(f, dtype=np.float64)
+    return lib().orc_teno5_right(_dp(f), eps, ct)

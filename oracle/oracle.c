@@ -36,6 +36,10 @@
 
 #define NEQ_MAX 8
 
+/* TENO5 cut-off C_T (not printed in the paper; the value published with the
+ * fifth-order TENO construction). */
+#define ORC_TENO_CT 1e-5
+
 typedef struct {
   int32_t ndim;
   int32_t n[3];
@@ -44,7 +48,7 @@ typedef struct {
   double dx[3];
   double gamma[2], pi_inf[2];
   double weno_eps;
-  int32_t weno_variant; /* 0: WENO5-JS (Sec. 3.2.1), 1: WENO5-Z (Sec. 4.2.2) */
+  int32_t weno_variant; /* 0: WENO5-JS (Sec. 3.2.1), 1: WENO5-Z, 2: TENO5 (Sec. 4.2.2) */
 } orc_problem;
 
 /* ------------------------------------------------------------------------ */
@@ -79,7 +83,7 @@ int orc_validate(const orc_problem* P) {
   for (int i = 0; i < P->num_fluids; ++i)
     if (!(P->gamma[i] > 1.0) || !(P->pi_inf[i] >= 0.0)) return ORC_ERR_ARG;
   if (!(P->weno_eps > 0)) return ORC_ERR_ARG;
-  if (P->weno_variant != 0 && P->weno_variant != 1) return ORC_ERR_ARG;
+  if (P->weno_variant < 0 || P->weno_variant > 2) return ORC_ERR_ARG;
   return ORC_OK;
 }
 
@@ -248,6 +252,41 @@ double orc_weno5_z_right(const double* f, double eps) {
 }
 
 /* ------------------------------------------------------------------------ */
+/* TENO5 (Sec. 4.2.2): the same three candidates and indicators; a stencil   */
+/* takes part (delta_r = 1) when its share chi_r = gamma_r / sum gamma of    */
+/* gamma_r = d_r (1 + tau/(beta_r + eps))^6 reaches the cut-off C_T, and the  */
+/* kept stencils combine with their linear weights, d_r delta_r / sum d delta.*/
+/* ------------------------------------------------------------------------ */
+static double pow6(double x) {
+  double x2 = x * x;
+  return x2 * x2 * x2;
+}
+
+double orc_teno5_left(const double* f, double eps, double ct) {
+  double a = f[0], b = f[1], c = f[2], d = f[3], e = f[4];
+  double q0 = (2.0 * a - 7.0 * b + 11.0 * c) / 6.0;
+  double q1 = (-b + 5.0 * c + 2.0 * d) / 6.0;
+  double q2 = (2.0 * c + 5.0 * d - e) / 6.0;
+  double b0 = 13.0 / 12.0 * sq((a + c) - 2.0 * b) + 0.25 * sq((a + 3.0 * c) - 4.0 * b);
+  double b1 = 13.0 / 12.0 * sq((b + d) - 2.0 * c) + 0.25 * sq(b - d);
+  double b2 = 13.0 / 12.0 * sq((c + e) - 2.0 * d) + 0.25 * sq((3.0 * c + e) - 4.0 * d);
+  double tau = fabs(b0 - b2);
+  double g0 = 0.1 * pow6(1.0 + tau / (b0 + eps));
+  double g1 = 0.6 * pow6(1.0 + tau / (b1 + eps));
+  double g2 = 0.3 * pow6(1.0 + tau / (b2 + eps));
+  double gs = g0 + g1 + g2;
+  double w0 = (g0 / gs >= ct) ? 0.1 : 0.0;
+  double w1 = (g1 / gs >= ct) ? 0.6 : 0.0;
+  double w2 = (g2 / gs >= ct) ? 0.3 : 0.0;
+  return (w0 * q0 + w1 * q1 + w2 * q2) / (w0 + w1 + w2);
+}
+
+double orc_teno5_right(const double* f, double eps, double ct) {
+  double r[5] = {f[4], f[3], f[2], f[1], f[0]};
+  return orc_teno5_left(r, eps, ct);
+}
+
+/* ------------------------------------------------------------------------ */
 /* HLLC face solver (Sec. 3.2.2; star states from Toro's book, the paper's  */
 /* reference for the solver).  Returns the flux of every row and the face   */
 /* velocity u_f that the non-conservative alpha term uses (Sec. 3.2.1: the  */
@@ -381,6 +420,9 @@ static int face_flux(const orc_problem* P, const double* q, int d, const int idx
     if (P->weno_variant == 1) {
       WL[v] = orc_weno5_z_left(fl, P->weno_eps);
       WR[v] = orc_weno5_z_right(fr, P->weno_eps);
+    } else if (P->weno_variant == 2) {
+      WL[v] = orc_teno5_left(fl, P->weno_eps, ORC_TENO_CT);
+      WR[v] = orc_teno5_right(fr, P->weno_eps, ORC_TENO_CT);
     } else {
       WL[v] = orc_weno5_js_left(fl, P->weno_eps);
       WR[v] = orc_weno5_js_right(fr, P->weno_eps);

@@ -184,6 +184,31 @@ def weno5_z_left(a, b, c, d, e, eps):
     return (a0 * q0 + a1 * q1 + a2 * q2) / (a0 + a1 + a2)
 
 
+TENO_CT = 1e-5
+
+
+def teno5_left(a, b, c, d, e, eps, ct=TENO_CT):
+    """TENO5 (Sec. 4.2.2): stencils whose share of gamma_r = d_r (1 + tau/(beta_r + eps))^6
+    reaches ct combine with their linear weights; the weights are piecewise constant."""
+    q0 = (2.0 * a - 7.0 * b + 11.0 * c) / 6.0
+    q1 = (-b + 5.0 * c + 2.0 * d) / 6.0
+    q2 = (2.0 * c + 5.0 * d - e) / 6.0
+    b0 = 13.0 / 12.0 * ((a + c) - 2.0 * b) ** 2 + 0.25 * ((a + 3.0 * c) - 4.0 * b) ** 2
+    b1 = 13.0 / 12.0 * ((b + d) - 2.0 * c) ** 2 + 0.25 * (b - d) ** 2
+    b2 = 13.0 / 12.0 * ((c + e) - 2.0 * d) ** 2 + 0.25 * ((3.0 * c + e) - 4.0 * d) ** 2
+    tau = torch.abs(b0 - b2)
+    p6 = lambda x: (x * x) * (x * x) * (x * x)
+    g0 = 0.1 * p6(1.0 + tau / (b0 + eps))
+    g1 = 0.6 * p6(1.0 + tau / (b1 + eps))
+    g2 = 0.3 * p6(1.0 + tau / (b2 + eps))
+    gs = g0 + g1 + g2
+    zero = torch.zeros_like(b0)
+    w0 = torch.where(g0 / gs >= ct, zero + 0.1, zero).detach()
+    w1 = torch.where(g1 / gs >= ct, zero + 0.6, zero).detach()
+    w2 = torch.where(g2 / gs >= ct, zero + 0.3, zero).detach()
+    return (w0 * q0 + w1 * q1 + w2 * q2) / (w0 + w1 + w2)
+
+
 def _min_first(a, b):
     return torch.where(a <= b, a, b)
 
@@ -260,7 +285,7 @@ def axis_contribution(P: Problem, q, d):
     # faces m - 1/2, m = 0..n; padded index of cell g is g + 3
     fl = [_sl(wp, ax, s, n + 1) for s in range(5)]       # centre m-1: cells m-3..m+1
     fr = [_sl(wp, ax, s + 1, n + 1) for s in range(5)]   # centre m: cells m-2..m+2
-    weno = weno5_z_left if P.weno_variant == 1 else weno5_js_left
+    weno = {0: weno5_js_left, 1: weno5_z_left, 2: teno5_left}[P.weno_variant]
     WL = weno(fl[0], fl[1], fl[2], fl[3], fl[4], P.eps)
     WR = weno(fr[4], fr[3], fr[2], fr[1], fr[0], P.eps)
     F, uf, _ = hllc(P, d, WL, WR)

@@ -256,6 +256,72 @@ def test_weno_z_fifth_order_advection_convergence():
 
 
 # --------------------------------------------------------------------------
+# TENO5 (Sec. 4.2.2): stencil kept when gamma_r / sum gamma >= C_T, weights d_r over the kept set
+# --------------------------------------------------------------------------
+def _linear5(f):
+    return (2 * f[0] - 13 * f[1] + 47 * f[2] + 27 * f[3] - 3 * f[4]) / 60.0
+
+
+def test_teno_smooth_data_is_exactly_the_linear_scheme():
+    """On smooth data every stencil's share is far above C_T, so the weights are
+    exactly (0.1, 0.6, 0.3): the value is the linear fifth-order one (rounding
+    only), unlike WENO-JS/Z whose weights stay data dependent."""
+    rng = np.random.default_rng(21)
+    h = 0.02
+    for _ in range(20):
+        coef = rng.normal(size=5)
+        f = np.array([_avg_poly(coef, (k - 2.5) * h, (k - 1.5) * h) for k in range(5)])
+        lin = _linear5(f)
+        assert abs(oracle.teno5_left(f) - lin) <= 8 * ULP * np.abs(f).max()
+        fr = f[::-1].copy()
+        assert abs(oracle.teno5_right(f) - _linear5(fr)) <= 8 * ULP * np.abs(f).max()
+
+
+def test_teno_vanishing_cutoff_keeps_every_stencil():
+    rng = np.random.default_rng(22)
+    for _ in range(100):
+        f = rng.normal(size=5) * rng.choice([1e-3, 1.0, 1e4])
+        f[rng.integers(0, 5)] += 10 * np.abs(f).max()
+        assert abs(oracle.teno5_left(f, ct=1e-300) - _linear5(f)) <= 16 * ULP * np.abs(f).max()
+
+
+def test_teno_step_selects_the_smooth_stencil():
+    """A jump inside two stencils cuts them: the value is the remaining smooth
+    candidate exactly (no oscillation)."""
+    assert oracle.teno5_left(np.array([0.0, 0.0, 0.0, 1.0, 1.0])) == 0.0
+    assert oracle.teno5_left(np.array([0.0, 0.0, 1.0, 1.0, 1.0])) == 1.0
+    assert oracle.teno5_left(np.array([2.0, 2.0, 2.0, -5.0, -5.0])) == 2.0
+
+
+def test_teno_quadratics_exact():
+    rng = np.random.default_rng(23)
+    h = 0.1
+    for _ in range(5):
+        coef = rng.normal(size=3)
+        f = np.array([_avg_poly(coef, (k - 2.5) * h, (k - 1.5) * h) for k in range(5)])
+        exact = sum(ck * (0.5 * h) ** k for k, ck in enumerate(coef))
+        assert abs(oracle.teno5_left(f) - exact) <= 1e-13 * (1 + abs(exact))
+
+
+def test_teno_fifth_order_advection_convergence():
+    """The paper's convergence problem (Sec. 3.5) with TENO5, which the paper
+    reports recovering its design order (Sec. 4.2.2)."""
+    errs = []
+    for N in (16, 32, 64):
+        c = W.advection_1d(N, amplitude=0.25, gamma2=1.6)
+        c.weno_variant = 2
+        O = oracle.Oracle(c)
+        q = O.prim_to_cons(c.w)
+        T, h = 5.0, 1.0 / N
+        ns = int(np.ceil(T / (0.25 * h ** (5.0 / 3.0))))
+        O.run(q, ns, dt_fixed=T / ns)
+        ex = W.advection_exact_average(N, 0.25, T)
+        errs.append(np.sqrt(np.mean((q[4, 0, 0] - ex) ** 2)))
+    orders = np.log2(np.array(errs[:-1]) / np.array(errs[1:]))
+    assert orders[-1] >= 4.5, orders
+
+
+# --------------------------------------------------------------------------
 # C-5: HLLC
 # --------------------------------------------------------------------------
 def _prim_state(rng, nf=2, D=3, speed=100.0):
@@ -453,7 +519,7 @@ def test_rhs_cells_matches_full_rhs_bitwise():
                                          (3, (12, 10, 9), 2, (1, 2, 0)), (1, (30,), 2, (2,))])
 def test_independent_torch_implementation_agrees_bitwise(nd, n, nf, bc):
     """The whole-array torch version (independent code) reproduces the oracle bit for bit."""
-    for variant in (0, 1):
+    for variant in (0, 1, 2):
         _torch_agrees(nd, n, nf, bc, variant)
 
 
