@@ -235,12 +235,13 @@ def periodic_slab_leg(n=512, steps=100, warmup=2):
     return out
 
 
-def weno_z_grind(case, steps=20, warmup=3):
-    """The same bubble cloud with WENO5-Z weights (Sec. 4.2.2): FP64 and FP32 grind."""
+def variant_grind(case, variant, steps=20, warmup=3):
+    """The same bubble cloud with the WENO5-Z (1) or TENO5 (2) weights of
+    Sec. 4.2.2: FP64 and FP32 grind."""
     import dataclasses
 
     from paper_2503_07953_amd.solver import Solver
-    cz = dataclasses.replace(case, weno_variant=1)
+    cz = dataclasses.replace(case, weno_variant=variant)
     out = {}
     for prec in ("fp64", "fp32"):
         S = Solver.from_case(cz, precision=prec)
@@ -347,7 +348,8 @@ def main():
     extra = None
     if not args.no_extra:
         extra = {"shock_cylinder_512_fp64_ns_per_cell_stage": shock_cylinder_grind(),
-                 "bubble_cloud_weno_z": weno_z_grind(case, args.steps, args.warmup)}
+                 "bubble_cloud_weno_z": variant_grind(case, 1, args.steps, args.warmup),
+                 "bubble_cloud_teno5": variant_grind(case, 2, args.steps, args.warmup)}
         log(f"extra: {extra}")
     slab = None
     if not args.no_slab:

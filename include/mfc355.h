@@ -70,11 +70,16 @@ enum { MFC_BC_PERIODIC = 0, MFC_BC_EXTRAP = 1, MFC_BC_SLIPWALL = 2 };
  * combination, the CFL reduction and the conservation sums. */
 enum { MFC_FP64 = 0, MFC_FP32_MIXED = 1 };
 
-/* Reconstruction weights: Jiang-Shu (Sec. 3.2.1) or the WENO-Z weights the
- * paper prints for order 5, a_k = d_k (1 + tau/(beta_k + eps)) with
- * tau = |beta_0 - beta_2| and exponent q = 1 (Sec. 4.2.2).  Both use the same
- * candidates, smoothness indicators, linear weights and eps. */
-enum { MFC_WENO_JS = 0, MFC_WENO_Z = 1 };
+/* Reconstruction weights, all on the same three candidates, smoothness
+ * indicators, linear weights d_k and eps:
+ *   MFC_WENO_JS  Jiang-Shu, d_k/(eps + beta_k)^2 (Sec. 3.2.1);
+ *   MFC_WENO_Z   d_k (1 + tau/(beta_k + eps)), tau = |beta_0 - beta_2|, q = 1
+ *                (Sec. 4.2.2);
+ *   MFC_TENO     stencil k kept when its share of gamma_k =
+ *                d_k (1 + tau/(beta_k + eps))^6 reaches C_T = 1e-5, kept
+ *                stencils weighted d_k (Sec. 4.2.2; the cut-off is not printed
+ *                there: the published fifth-order value). */
+enum { MFC_WENO_JS = 0, MFC_WENO_Z = 1, MFC_TENO = 2 };
 
 typedef struct {
   int32_t abi_version; /* must equal MFC_ABI_VERSION */
@@ -89,7 +94,7 @@ typedef struct {
   double gamma[2];     /* stiffened-gas gamma_i > 1 per fluid (Sec. 2.2) */
   double pi_inf[2];    /* stiffened-gas pi_inf,i >= 0 per fluid */
   double weno_eps;     /* WENO smoothness regularization, > 0 (1e-6) */
-  int32_t weno_variant; /* MFC_WENO_JS or MFC_WENO_Z */
+  int32_t weno_variant; /* MFC_WENO_JS, MFC_WENO_Z or MFC_TENO */
 } mfc_problem;
 
 typedef struct mfc_ctx mfc_ctx;

@@ -197,6 +197,43 @@ __host__ __device__ __forceinline__ void weno_z_left_vjp(double a, double b, dou
   g[4] += gD3;
 }
 
+// Adjoint of the left-biased TENO5 value (Sec. 4.2.2): the kept set is decided
+// exactly as in the forward reconstruction and the weights are then constant,
+// so y = c + sum_k w_k l_k / 6 with w_k = d_k delta_k / sum d delta is linear
+// in the differences.  Accumulates g[0..4].
+__host__ __device__ __forceinline__ void teno_left_vjp(double a, double b, double c, double d, double e,
+                                                       double eps, double gy, double* g) {
+  const double D0 = b - a, D1 = c - b, D2 = d - c, D3 = e - d;
+  const double u0 = D1 - D0, v0 = 3.0 * D1 - D0;
+  const double u1 = D2 - D1, v1 = D1 + D2;
+  const double u2 = D3 - D2, v2 = D3 - 3.0 * D2;
+  const double e4 = 4.0 * eps;
+  const double s0 = e4 + ((13.0 / 3.0) * u0 * u0 + v0 * v0);
+  const double s1 = e4 + ((13.0 / 3.0) * u1 * u1 + v1 * v1);
+  const double s2 = e4 + ((13.0 / 3.0) * u2 * u2 + v2 * v2);
+  const double tau = fabs(s0 - s2);
+  const double m0 = s1 * s2, m1 = s0 * s2, m2 = s0 * s1;
+  const double rP = fast_rcp(s0 * m0);
+  const double x0 = 1.0 + tau * (m0 * rP), x1 = 1.0 + tau * (m1 * rP), x2 = 1.0 + tau * (m2 * rP);
+  const double g0 = 0.1 * ((x0 * x0) * (x0 * x0) * (x0 * x0));
+  const double g1 = 0.6 * ((x1 * x1) * (x1 * x1) * (x1 * x1));
+  const double g2 = 0.3 * ((x2 * x2) * (x2 * x2) * (x2 * x2));
+  const double cut = kTenoCt * (g0 + g1 + g2);
+  const double w0 = g0 >= cut ? 0.1 : 0.0, w1 = g1 >= cut ? 0.6 : 0.0, w2 = g2 >= cut ? 0.3 : 0.0;
+  const double gk = gy * fast_rcp(6.0 * (w0 + w1 + w2));
+  const double gl0 = gk * w0, gl1 = gk * w1, gl2 = gk * w2;
+  // l_0 = 5D1 - 2D0, l_1 = D1 + 2D2, l_2 = 4D2 - D3
+  const double gD0 = -2.0 * gl0;
+  const double gD1 = 5.0 * gl0 + gl1;
+  const double gD2 = 2.0 * gl1 + 4.0 * gl2;
+  const double gD3 = -gl2;
+  g[0] -= gD0;
+  g[1] += gD0 - gD1;
+  g[2] += gy + gD1 - gD2;
+  g[3] += gD2 - gD3;
+  g[4] += gD3;
+}
+
 // Adjoint of one reconstruction centre: gL is the cotangent of the left-biased
 // value at i+1/2, gR of the right-biased value at i-1/2 (the mirror image).
 __host__ __device__ __forceinline__ void weno5_js_vjp(const double* f, double eps, double gL, double gR, double* g) {

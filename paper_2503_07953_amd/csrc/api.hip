@@ -200,7 +200,7 @@ mfc::Params make_params(const mfc_problem& p) {
     pm.P[i] = p.gamma[k] * p.pi_inf[k] / (p.gamma[k] - 1.0);
   }
   pm.eps = p.weno_eps;
-  pm.weno_z = (p.weno_variant == MFC_WENO_Z) ? 1 : 0;
+  pm.weno_variant = p.weno_variant;
   pm.ncell = (long long)p.n[0] * p.n[1] * p.n[2];
   return pm;
 }
@@ -258,7 +258,7 @@ int mfc_validate(const mfc_problem* p) {
   for (int i = 0; i < p->num_fluids; ++i)
     if (!(p->gamma[i] > 1.0) || !(p->pi_inf[i] >= 0.0) || !(p->pi_inf[i] < 1e300)) return MFC_ERR_ARG;
   if (!(p->weno_eps > 0.0)) return MFC_ERR_ARG;
-  if (p->weno_variant != MFC_WENO_JS && p->weno_variant != MFC_WENO_Z) return MFC_ERR_UNSUPPORTED;
+  if (p->weno_variant < MFC_WENO_JS || p->weno_variant > MFC_TENO) return MFC_ERR_UNSUPPORTED;
   return MFC_OK;
 }
 

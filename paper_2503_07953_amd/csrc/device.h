@@ -19,7 +19,7 @@ struct Params {
   int n[3];            // interior cells per axis (unused axes: 1)
   int bc_lo[3];        // BC kind per axis, low side
   int bc_hi[3];        // BC kind per axis, high side
-  int weno_z;          // 1: WENO5-Z weights (Sec. 4.2.2), 0: WENO5-JS
+  int weno_variant;    // 0: WENO5-JS (Sec. 3.2.1), 1: WENO5-Z, 2: TENO5 (Sec. 4.2.2)
   double inv_dx[3];    // 1/dx per axis
   double G[2];         // 1/(gamma_i - 1)
   double P[2];         // gamma_i pi_inf,i/(gamma_i - 1)
@@ -253,13 +253,87 @@ __device__ __forceinline__ void weno5_z(float a, float b, float c, float d, floa
   fr = c + (wr0 * r0 + w1 * r1 + wr2 * r2) * __builtin_amdgcn_rcpf(6.0f * (wr0 + w1 + wr2));
 }
 
-// The reconstruction of a kernel instantiation: WZ selects WENO5-Z, else JS.
-// (A compile-time choice: a run-time branch inside the unrolled row loops
-// would make every kernel hold the registers of both.)
-template <bool WZ, typename T>
+// TENO5 (Sec. 4.2.2): the same candidates and indicators; stencil k is kept
+// when its share of gamma_k = d_k (1 + tau/(beta_k + eps))^6 reaches the
+// cut-off kTenoCt, and the kept stencils combine with their linear weights.
+// In terms of s_k = 4 (eps + beta_k): 1 + tau/(beta_k + eps) = 1 + tau'/s_k
+// with tau' = |s_0 - s_2|.  The shares are compared as gamma_k >= C_T sum gamma.
+constexpr double kTenoCt = 1e-5;
+
+__host__ __device__ __forceinline__ void teno5(double a, double b, double c, double d, double e, double eps,
+                                               double& fl, double& fr) {
+  const double D0 = b - a, D1 = c - b, D2 = d - c, D3 = e - d;
+  const double u0 = D1 - D0, v0 = 3.0 * D1 - D0;
+  const double u1 = D2 - D1, v1 = D1 + D2;
+  const double u2 = D3 - D2, v2 = D3 - 3.0 * D2;
+  const double e4 = 4.0 * eps;
+  const double s0 = e4 + ((13.0 / 3.0) * u0 * u0 + v0 * v0);
+  const double s1 = e4 + ((13.0 / 3.0) * u1 * u1 + v1 * v1);
+  const double s2 = e4 + ((13.0 / 3.0) * u2 * u2 + v2 * v2);
+  const double tau = fabs(s0 - s2);
+  const double m0 = s1 * s2, m1 = s0 * s2, m2 = s0 * s1;
+  const double rP = fast_rcp(s0 * m0);
+  const double x0 = 1.0 + tau * (m0 * rP), x1 = 1.0 + tau * (m1 * rP), x2 = 1.0 + tau * (m2 * rP);
+  const double p0 = (x0 * x0) * (x0 * x0) * (x0 * x0);
+  const double p1 = (x1 * x1) * (x1 * x1) * (x1 * x1);
+  const double p2 = (x2 * x2) * (x2 * x2) * (x2 * x2);
+  const double l0 = 5.0 * D1 - 2.0 * D0, l1 = D1 + 2.0 * D2, l2 = 4.0 * D2 - D3;
+  const double r0 = 2.0 * D3 - 5.0 * D2, r1 = -(D2 + 2.0 * D1), r2 = D0 - 4.0 * D1;
+  // left: linear weights (0.1, 0.6, 0.3) on stencils (0, 1, 2); right: mirrored
+  const double gl0 = 0.1 * p0, g1 = 0.6 * p1, gl2 = 0.3 * p2;
+  const double gr0 = 0.1 * p2, gr2 = 0.3 * p0;
+  const double cl = kTenoCt * (gl0 + g1 + gl2), cr = kTenoCt * (gr0 + g1 + gr2);
+  const double wl0 = gl0 >= cl ? 0.1 : 0.0, wl1 = g1 >= cl ? 0.6 : 0.0, wl2 = gl2 >= cl ? 0.3 : 0.0;
+  const double wr0 = gr0 >= cr ? 0.1 : 0.0, wr1 = g1 >= cr ? 0.6 : 0.0, wr2 = gr2 >= cr ? 0.3 : 0.0;
+  const double inv = fast_rcp(6.0 * ((wl0 + wl1 + wl2) * (wr0 + wr1 + wr2)));
+  fl = c + (wl0 * l0 + wl1 * l1 + wl2 * l2) * ((wr0 + wr1 + wr2) * inv);
+  fr = c + (wr0 * r0 + wr1 * r1 + wr2 * r2) * ((wl0 + wl1 + wl2) * inv);
+}
+
+// FP32 TENO5: x_k = 1 + tau'/s_k is scaled by its maximum before the sixth
+// power (which would overflow float); the shares are unchanged by the scale.
+__device__ __forceinline__ void teno5(float a, float b, float c, float d, float e, float eps, float& fl,
+                                      float& fr) {
+  const float D0 = b - a, D1 = c - b, D2 = d - c, D3 = e - d;
+  const float u0 = D1 - D0, v0 = 3.0f * D1 - D0;
+  const float u1 = D2 - D1, v1 = D1 + D2;
+  const float u2 = D3 - D2, v2 = D3 - 3.0f * D2;
+  const float e4 = 4.0f * eps;
+  const float s0 = e4 + ((13.0f / 3.0f) * u0 * u0 + v0 * v0);
+  const float s1 = e4 + ((13.0f / 3.0f) * u1 * u1 + v1 * v1);
+  const float s2 = e4 + ((13.0f / 3.0f) * u2 * u2 + v2 * v2);
+  const float tau = fabsf(s0 - s2);
+  float x0 = 1.0f + tau * __builtin_amdgcn_rcpf(s0);
+  float x1 = 1.0f + tau * __builtin_amdgcn_rcpf(s1);
+  float x2 = 1.0f + tau * __builtin_amdgcn_rcpf(s2);
+  const float xm = __builtin_amdgcn_rcpf(fmaxf(x0, fmaxf(x1, x2)));
+  x0 *= xm;
+  x1 *= xm;
+  x2 *= xm;
+  const float p0 = (x0 * x0) * (x0 * x0) * (x0 * x0);
+  const float p1 = (x1 * x1) * (x1 * x1) * (x1 * x1);
+  const float p2 = (x2 * x2) * (x2 * x2) * (x2 * x2);
+  const float l0 = 5.0f * D1 - 2.0f * D0, l1 = D1 + 2.0f * D2, l2 = 4.0f * D2 - D3;
+  const float r0 = 2.0f * D3 - 5.0f * D2, r1 = -(D2 + 2.0f * D1), r2 = D0 - 4.0f * D1;
+  const float gl0 = 0.1f * p0, g1 = 0.6f * p1, gl2 = 0.3f * p2;
+  const float gr0 = 0.1f * p2, gr2 = 0.3f * p0;
+  const float ct = float(kTenoCt);
+  const float cl = ct * (gl0 + g1 + gl2), cr = ct * (gr0 + g1 + gr2);
+  const float wl0 = gl0 >= cl ? 0.1f : 0.0f, wl1 = g1 >= cl ? 0.6f : 0.0f, wl2 = gl2 >= cl ? 0.3f : 0.0f;
+  const float wr0 = gr0 >= cr ? 0.1f : 0.0f, wr1 = g1 >= cr ? 0.6f : 0.0f, wr2 = gr2 >= cr ? 0.3f : 0.0f;
+  fl = c + (wl0 * l0 + wl1 * l1 + wl2 * l2) * __builtin_amdgcn_rcpf(6.0f * (wl0 + wl1 + wl2));
+  fr = c + (wr0 * r0 + wr1 * r1 + wr2 * r2) * __builtin_amdgcn_rcpf(6.0f * (wr0 + wr1 + wr2));
+}
+
+// The reconstruction of a kernel instantiation: WV = 0 WENO5-JS, 1 WENO5-Z,
+// 2 TENO5.  (A compile-time choice: a run-time branch inside the unrolled row
+// loops would make every kernel hold the registers of all of them.)
+template <int WV, typename T>
 __device__ __forceinline__ void weno5(T a, T b, T c, T d, T e, T eps, T& fl, T& fr) {
-  if constexpr (WZ)
+  if constexpr (WV == 1)
     weno5_z(a, b, c, d, e, eps, fl, fr);
+  else if constexpr (WV == 2)
+    teno5(a, b, c, d, e, eps, fl, fr);
   else
     weno5_js(a, b, c, d, e, eps, fl, fr);
 }

@@ -50,7 +50,7 @@ __device__ __forceinline__ int lds_index(int v, int s, int b) {
     return (v * TL::SA + s) * TL::TB + b;
 }
 
-template <int NF, int D, int DIR, typename Real, int MODE, bool WZ>
+template <int NF, int D, int DIR, typename Real, int MODE, int WV>
 __global__ __launch_bounds__((Tile<DIR, D, Real>::NT)) void sweep_kernel(Params pm, const Real* __restrict__ qk,
                                                                  Real* __restrict__ acc,
                                                                  const Real* __restrict__ qn,
@@ -150,7 +150,7 @@ __global__ __launch_bounds__((Tile<DIR, D, Real>::NT)) void sweep_kernel(Params 
       const Real f2 = sh[lds_index<DIR, D, Real>(v, a + 2, b)];
       const Real f3 = sh[lds_index<DIR, D, Real>(v, a + 3, b)];
       const Real f4 = sh[lds_index<DIR, D, Real>(v, a + 4, b)];
-      weno5<WZ>(f0, f1, f2, f3, f4, eps, WLc[v], WRc[v]);
+      weno5<WV>(f0, f1, f2, f3, f4, eps, WLc[v], WRc[v]);
     }
     if constexpr (NF == 2) {
       alpha_cell[0] = sh[lds_index<DIR, D, Real>(R::ALPHA, a + 2, b)];
@@ -223,7 +223,7 @@ __global__ __launch_bounds__((Tile<DIR, D, Real>::NT)) void sweep_kernel(Params 
 // ---------------------------------------------------------------------------
 // host launchers
 // ---------------------------------------------------------------------------
-template <int NF, int D, int DIR, typename Real, int MODE, bool WZ>
+template <int NF, int D, int DIR, typename Real, int MODE, int WV>
 static hipError_t launch_one(const Params& pm, const Real* qk, Real* acc, const Real* qn, Real* qout,
                              StageArgs st, int* flag, hipStream_t s, PassTimer* tm) {
   using TL = Tile<DIR, D, Real>;
@@ -240,34 +240,34 @@ static hipError_t launch_one(const Params& pm, const Real* qk, Real* acc, const 
     grid = dim3((nx + TL::TB - 1) / TL::TB, ny, (nz + TL::OUT - 1) / TL::OUT);
   }
   if (tm) tm->begin(KIND_PASS_X + DIR, s);
-  hipLaunchKernelGGL((sweep_kernel<NF, D, DIR, Real, MODE, WZ>), grid, block, 0, s, pm, qk, acc, qn, qout, st,
+  hipLaunchKernelGGL((sweep_kernel<NF, D, DIR, Real, MODE, WV>), grid, block, 0, s, pm, qk, acc, qn, qout, st,
                      flag);
   if (tm) tm->end(KIND_PASS_X + DIR, s);
   return hipGetLastError();
 }
 
 // All axes of one RHS evaluation.  final_step: the last axis combines into qout.
-template <int NF, int D, typename Real, bool WZ>
+template <int NF, int D, typename Real, int WV>
 static hipError_t launch_rhs_t(const Params& pm, const Real* qk, Real* acc, const Real* qn, Real* qout,
                                StageArgs st, bool final_step, int* flag, hipStream_t s, PassTimer* tm) {
   hipError_t e = hipSuccess;
   if constexpr (D == 1) {
     if (final_step)
-      e = launch_one<NF, D, 0, Real, MODE_STEP, WZ>(pm, qk, acc, qn, qout, st, flag, s, tm);
+      e = launch_one<NF, D, 0, Real, MODE_STEP, WV>(pm, qk, acc, qn, qout, st, flag, s, tm);
     else
-      e = launch_one<NF, D, 0, Real, MODE_WRITE, WZ>(pm, qk, acc, qn, qout, st, flag, s, tm);
+      e = launch_one<NF, D, 0, Real, MODE_WRITE, WV>(pm, qk, acc, qn, qout, st, flag, s, tm);
   } else {
-    e = launch_one<NF, D, 0, Real, MODE_WRITE, WZ>(pm, qk, acc, qn, qout, st, flag, s, tm);
+    e = launch_one<NF, D, 0, Real, MODE_WRITE, WV>(pm, qk, acc, qn, qout, st, flag, s, tm);
     if (e != hipSuccess) return e;
     if constexpr (D == 3) {
-      e = launch_one<NF, D, 1, Real, MODE_ACC, WZ>(pm, qk, acc, qn, qout, st, flag, s, tm);
+      e = launch_one<NF, D, 1, Real, MODE_ACC, WV>(pm, qk, acc, qn, qout, st, flag, s, tm);
       if (e != hipSuccess) return e;
     }
     constexpr int LAST = D - 1;
     if (final_step)
-      e = launch_one<NF, D, LAST, Real, MODE_ACC | MODE_STEP, WZ>(pm, qk, acc, qn, qout, st, flag, s, tm);
+      e = launch_one<NF, D, LAST, Real, MODE_ACC | MODE_STEP, WV>(pm, qk, acc, qn, qout, st, flag, s, tm);
     else
-      e = launch_one<NF, D, LAST, Real, MODE_ACC, WZ>(pm, qk, acc, qn, qout, st, flag, s, tm);
+      e = launch_one<NF, D, LAST, Real, MODE_ACC, WV>(pm, qk, acc, qn, qout, st, flag, s, tm);
   }
   return e;
 }
@@ -277,8 +277,9 @@ hipError_t launch_rhs(int nf, int ndim, const Params& pm, const Real* qk, Real* 
                       Real* qout, StageArgs st, bool final_step, int* flag, hipStream_t s, PassTimer* tm) {
 #define MFC_CASE(NF, D)                                                                        \
   if (nf == NF && ndim == D)                                                                   \
-    return pm.weno_z ? launch_rhs_t<NF, D, Real, true>(pm, qk, acc, qn, qout, st, final_step, flag, s, tm)  \
-                     : launch_rhs_t<NF, D, Real, false>(pm, qk, acc, qn, qout, st, final_step, flag, s, tm);
+    return pm.weno_variant == 1   ? launch_rhs_t<NF, D, Real, 1>(pm, qk, acc, qn, qout, st, final_step, flag, s, tm) \
+           : pm.weno_variant == 2 ? launch_rhs_t<NF, D, Real, 2>(pm, qk, acc, qn, qout, st, final_step, flag, s, tm) \
+                                  : launch_rhs_t<NF, D, Real, 0>(pm, qk, acc, qn, qout, st, final_step, flag, s, tm);
   MFC_CASE(1, 1)
   MFC_CASE(1, 2)
   MFC_CASE(1, 3)

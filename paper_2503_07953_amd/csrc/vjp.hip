@@ -99,7 +99,7 @@ __host__ __device__ __forceinline__ void face_grid(const int* n, int& g0, int& g
 // One face tile of axis DIR (tile coordinates t0, t1, t2 as in face_grid):
 // face cotangents, HLLC^T and WENO^T, writing the six stencil positions'
 // primitive cotangents of every face to G and the forward face velocity to UF.
-template <int NF, int D, int DIR, bool WZ>
+template <int NF, int D, int DIR, int WV>
 __device__ __forceinline__ void face_tile(const Params pm, const double* __restrict__ q,
                                           const double* __restrict__ rbar, double* __restrict__ G,
                                           double* __restrict__ UF, const AxisGeom& fg, int t0, int t1, int t2,
@@ -189,8 +189,8 @@ __device__ __forceinline__ void face_tile(const Params pm, const double* __restr
 #pragma unroll
   for (int v = 0; v < NEQ; ++v) {
     double l, r, t;
-    weno5<WZ>(Ws(0, v), Ws(1, v), Ws(2, v), Ws(3, v), Ws(4, v), pm.eps, l, t);
-    weno5<WZ>(Ws(1, v), Ws(2, v), Ws(3, v), Ws(4, v), Ws(5, v), pm.eps, t, r);
+    weno5<WV>(Ws(0, v), Ws(1, v), Ws(2, v), Ws(3, v), Ws(4, v), pm.eps, l, t);
+    weno5<WV>(Ws(1, v), Ws(2, v), Ws(3, v), Ws(4, v), Ws(5, v), pm.eps, t, r);
     WL[v] = l;
     WR[v] = r;
   }
@@ -208,9 +208,12 @@ __device__ __forceinline__ void face_tile(const Params pm, const double* __restr
   for (int v = 0; v < NEQ; ++v) {
     double g[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     double gr[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-    if constexpr (WZ) {
+    if constexpr (WV == 1) {
       weno_z_left_vjp(Ws(0, v), Ws(1, v), Ws(2, v), Ws(3, v), Ws(4, v), pm.eps, WLb[v], g);
       weno_z_left_vjp(Ws(5, v), Ws(4, v), Ws(3, v), Ws(2, v), Ws(1, v), pm.eps, WRb[v], gr);
+    } else if constexpr (WV == 2) {
+      teno_left_vjp(Ws(0, v), Ws(1, v), Ws(2, v), Ws(3, v), Ws(4, v), pm.eps, WLb[v], g);
+      teno_left_vjp(Ws(5, v), Ws(4, v), Ws(3, v), Ws(2, v), Ws(1, v), pm.eps, WRb[v], gr);
     } else {
       weno_left_vjp(Ws(0, v), Ws(1, v), Ws(2, v), Ws(3, v), Ws(4, v), pm.eps, WLb[v], g);
       weno_left_vjp(Ws(5, v), Ws(4, v), Ws(3, v), Ws(2, v), Ws(1, v), pm.eps, WRb[v], gr);
@@ -244,19 +247,19 @@ __device__ __forceinline__ void unflatten_tile(int w, const Params& pm, int& t0,
 }
 
 // Face pass of one axis (sequential path).
-template <int NF, int D, int DIR, bool WZ>
+template <int NF, int D, int DIR, int WV>
 __global__ __launch_bounds__(kFaceThreads) void vjp_face_kernel(Params pm, const double* __restrict__ q,
                                                                const double* __restrict__ rbar,
                                                                double* __restrict__ G, double* __restrict__ UF) {
   __shared__ double sw[FaceLds<Rows<NF, D>::NEQ>::size];
   int t0, t1, t2;
   unflatten_tile<DIR>(blockIdx.x, pm, t0, t1, t2);
-  face_tile<NF, D, DIR, WZ>(pm, q, rbar, G, UF, face_geom<DIR>(pm), t0, t1, t2, threadIdx.x, sw);
+  face_tile<NF, D, DIR, WV>(pm, q, rbar, G, UF, face_geom<DIR>(pm), t0, t1, t2, threadIdx.x, sw);
 }
 
 // Face passes of every axis in one launch: blocks [0, nb[0]) take x tiles,
 // the next nb[1] y tiles, then z.  Each axis writes its own G and UF.
-template <int NF, int D, bool WZ>
+template <int NF, int D, int WV>
 __global__ __launch_bounds__(kFaceThreads) void vjp_faces_all_kernel(Params pm, const double* __restrict__ q,
                                                                     const double* __restrict__ rbar, VjpScratch sc,
                                                                     int nb0, int nb1) {
@@ -264,21 +267,21 @@ __global__ __launch_bounds__(kFaceThreads) void vjp_faces_all_kernel(Params pm, 
   int w = blockIdx.x, t0, t1, t2;
   if (w < nb0) {
     unflatten_tile<0>(w, pm, t0, t1, t2);
-    face_tile<NF, D, 0, WZ>(pm, q, rbar, sc.Gd[0], sc.UFd[0], face_geom<0>(pm), t0, t1, t2, threadIdx.x, sw);
+    face_tile<NF, D, 0, WV>(pm, q, rbar, sc.Gd[0], sc.UFd[0], face_geom<0>(pm), t0, t1, t2, threadIdx.x, sw);
     return;
   }
   w -= nb0;
   if constexpr (D > 1) {
     if (w < nb1) {
       unflatten_tile<1>(w, pm, t0, t1, t2);
-      face_tile<NF, D, 1, WZ>(pm, q, rbar, sc.Gd[1], sc.UFd[1], face_geom<1>(pm), t0, t1, t2, threadIdx.x, sw);
+      face_tile<NF, D, 1, WV>(pm, q, rbar, sc.Gd[1], sc.UFd[1], face_geom<1>(pm), t0, t1, t2, threadIdx.x, sw);
       return;
     }
     w -= nb1;
   }
   if constexpr (D > 2) {
     unflatten_tile<2>(w, pm, t0, t1, t2);
-    face_tile<NF, D, 2, WZ>(pm, q, rbar, sc.Gd[2], sc.UFd[2], face_geom<2>(pm), t0, t1, t2, threadIdx.x, sw);
+    face_tile<NF, D, 2, WV>(pm, q, rbar, sc.Gd[2], sc.UFd[2], face_geom<2>(pm), t0, t1, t2, threadIdx.x, sw);
   }
 }
 
@@ -391,10 +394,10 @@ static int face_blocks(const Params& pm) {
 
 // Sequential path: per axis, its face pass into the shared buffer Gd[0] /
 // UFd[0], then its cell pass.
-template <int NF, int D, int DIR, bool WZ>
+template <int NF, int D, int DIR, int WV>
 static hipError_t launch_axis_vjp(const Params& pm, const double* q, const double* rbar, double* qbar,
                                   VjpScratch sc, bool accumulate, hipStream_t s) {
-  hipLaunchKernelGGL((vjp_face_kernel<NF, D, DIR, WZ>), dim3((unsigned)face_blocks<DIR>(pm)), dim3(kFaceThreads), 0, s,
+  hipLaunchKernelGGL((vjp_face_kernel<NF, D, DIR, WV>), dim3((unsigned)face_blocks<DIR>(pm)), dim3(kFaceThreads), 0, s,
                      pm, q, rbar, sc.Gd[0], sc.UFd[0]);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
@@ -407,7 +410,7 @@ static hipError_t launch_axis_vjp(const Params& pm, const double* q, const doubl
   return hipGetLastError();
 }
 
-template <int NF, int D, bool WZ>
+template <int NF, int D, int WV>
 static hipError_t launch_rhs_vjp_t(const Params& pm, const double* q, const double* rbar, double* qbar,
                                    const VjpScratch& sc, bool accumulate, hipStream_t s, PassTimer* tm) {
   hipError_t e = hipSuccess;
@@ -417,7 +420,7 @@ static hipError_t launch_rhs_vjp_t(const Params& pm, const double* q, const doub
     const int nb0 = face_blocks<0>(pm);
     const int nb1 = D > 1 ? face_blocks<(D > 1 ? 1 : 0)>(pm) : 0;
     const int nb2 = D > 2 ? face_blocks<(D > 2 ? 2 : 0)>(pm) : 0;
-    hipLaunchKernelGGL((vjp_faces_all_kernel<NF, D, WZ>), dim3((unsigned)(nb0 + nb1 + nb2)), dim3(kFaceThreads), 0, s, pm,
+    hipLaunchKernelGGL((vjp_faces_all_kernel<NF, D, WV>), dim3((unsigned)(nb0 + nb1 + nb2)), dim3(kFaceThreads), 0, s, pm,
                        q, rbar, sc, nb0, nb1);
     e = hipGetLastError();
     if (e == hipSuccess) {
@@ -426,9 +429,9 @@ static hipError_t launch_rhs_vjp_t(const Params& pm, const double* q, const doub
       e = hipGetLastError();
     }
   } else {
-    e = launch_axis_vjp<NF, D, 0, WZ>(pm, q, rbar, qbar, sc, accumulate, s);
-    if (e == hipSuccess && D > 1) e = launch_axis_vjp<NF, D, (D > 1 ? 1 : 0), WZ>(pm, q, rbar, qbar, sc, true, s);
-    if (e == hipSuccess && D > 2) e = launch_axis_vjp<NF, D, (D > 2 ? 2 : 0), WZ>(pm, q, rbar, qbar, sc, true, s);
+    e = launch_axis_vjp<NF, D, 0, WV>(pm, q, rbar, qbar, sc, accumulate, s);
+    if (e == hipSuccess && D > 1) e = launch_axis_vjp<NF, D, (D > 1 ? 1 : 0), WV>(pm, q, rbar, qbar, sc, true, s);
+    if (e == hipSuccess && D > 2) e = launch_axis_vjp<NF, D, (D > 2 ? 2 : 0), WV>(pm, q, rbar, qbar, sc, true, s);
   }
   if (tm) tm->end(KIND_VJP, s);
   return e;
@@ -438,8 +441,9 @@ hipError_t launch_rhs_vjp(int nf, int ndim, const Params& pm, const double* q, c
                           const VjpScratch& sc, bool accumulate, hipStream_t s, PassTimer* tm) {
 #define MFC_CASE(NF, D)                                                                   \
   if (nf == NF && ndim == D)                                                              \
-    return pm.weno_z ? launch_rhs_vjp_t<NF, D, true>(pm, q, rbar, qbar, sc, accumulate, s, tm) \
-                     : launch_rhs_vjp_t<NF, D, false>(pm, q, rbar, qbar, sc, accumulate, s, tm);
+    return pm.weno_variant == 1   ? launch_rhs_vjp_t<NF, D, 1>(pm, q, rbar, qbar, sc, accumulate, s, tm) \
+           : pm.weno_variant == 2 ? launch_rhs_vjp_t<NF, D, 2>(pm, q, rbar, qbar, sc, accumulate, s, tm) \
+                                  : launch_rhs_vjp_t<NF, D, 0>(pm, q, rbar, qbar, sc, accumulate, s, tm);
   MFC_CASE(1, 1)
   MFC_CASE(1, 2)
   MFC_CASE(1, 3)

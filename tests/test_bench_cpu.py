@@ -13,7 +13,7 @@ import bench  # noqa: E402
 
 def test_bench_defines_every_leg():
     for name in ("time_steps", "adjoint_cost", "roofline_of", "field_group_errors", "periodic_slab_leg",
-                 "shock_cylinder_grind", "weno_z_grind", "measured_traffic_bytes", "main"):
+                 "shock_cylinder_grind", "variant_grind", "measured_traffic_bytes", "main"):
         assert callable(getattr(bench, name)), name
 
 
