@@ -73,6 +73,9 @@ def lib():
             "orc_weno5_js_right": (ctypes.c_double, [dp, ctypes.c_double]),
             "orc_weno5_z_left": (ctypes.c_double, [dp, ctypes.c_double]),
             "orc_weno5_z_right": (ctypes.c_double, [dp, ctypes.c_double]),
+            "orc_weno5_m_left": (ctypes.c_double, [dp, ctypes.c_double]),
+            "orc_weno5_m_right": (ctypes.c_double, [dp, ctypes.c_double]),
+            "orc_weno_m_map": (ctypes.c_double, [ctypes.c_double, ctypes.c_double]),
             "orc_teno5_left": (ctypes.c_double, [dp, ctypes.c_double, ctypes.c_double]),
             "orc_teno5_right": (ctypes.c_double, [dp, ctypes.c_double, ctypes.c_double]),
             "orc_hllc": (ctypes.c_int, [P, ctypes.c_int, dp, dp, dp, dp]),
@@ -251,6 +254,22 @@ def weno5_z_left(f, eps=1e-6):
 def weno5_z_right(f, eps=1e-6):
     f = np.ascontiguousarray(f, dtype=np.float64)
     return lib().orc_weno5_z_right(_dp(f), eps)
+
+
+def weno5_m_left(f, eps=1e-6):
+    """Left-biased WENO5-M value (mapped JS weights, Sec. 3.2.1) from f[0..4]."""
+    f = np.ascontiguousarray(f, dtype=np.float64)
+    return lib().orc_weno5_m_left(_dp(f), eps)
+
+
+def weno5_m_right(f, eps=1e-6):
+    f = np.ascontiguousarray(f, dtype=np.float64)
+    return lib().orc_weno5_m_right(_dp(f), eps)
+
+
+def weno_m_map(w, d):
+    """The weight map g_d(w) of WENO5-M."""
+    return lib().orc_weno_m_map(float(w), float(d))
 
 
 TENO_CT = 1e-5

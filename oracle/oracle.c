@@ -48,7 +48,7 @@ typedef struct {
   double dx[3];
   double gamma[2], pi_inf[2];
   double weno_eps;
-  int32_t weno_variant; /* 0: WENO5-JS (Sec. 3.2.1), 1: WENO5-Z, 2: TENO5 (Sec. 4.2.2) */
+  int32_t weno_variant; /* 0: WENO5-JS (Sec. 3.2.1), 1: WENO5-Z, 2: TENO5 (Sec. 4.2.2), 3: WENO5-M (Sec. 3.2.1) */
 } orc_problem;
 
 /* ------------------------------------------------------------------------ */
@@ -83,7 +83,7 @@ int orc_validate(const orc_problem* P) {
   for (int i = 0; i < P->num_fluids; ++i)
     if (!(P->gamma[i] > 1.0) || !(P->pi_inf[i] >= 0.0)) return ORC_ERR_ARG;
   if (!(P->weno_eps > 0)) return ORC_ERR_ARG;
-  if (P->weno_variant < 0 || P->weno_variant > 2) return ORC_ERR_ARG;
+  if (P->weno_variant < 0 || P->weno_variant > 3) return ORC_ERR_ARG;
   return ORC_OK;
 }
 
@@ -249,6 +249,41 @@ double orc_weno5_z_left(const double* f, double eps) {
 double orc_weno5_z_right(const double* f, double eps) {
   double r[5] = {f[4], f[3], f[2], f[1], f[0]};
   return orc_weno5_z_left(r, eps);
+}
+
+/* ------------------------------------------------------------------------ */
+/* WENO5-M.  Sec. 3.2.1 keeps fifth order through the mapped weights of      */
+/* Henrick, Aslam and Powers (2005), which it cites without printing them.   */
+/* Their definition: the JS weights w_k = a_k / sum a are mapped by           */
+/*   g_k(w) = w (d_k + d_k^2 - 3 d_k w + w^2) / (d_k^2 + w (1 - 2 d_k)),     */
+/* which fixes 0, d_k and 1 and is flat to second order at d_k, and the       */
+/* mapped values are normalized again.  Same candidates, indicators and eps. */
+/* ------------------------------------------------------------------------ */
+double orc_weno_m_map(double w, double d) {
+  return w * (d + d * d - 3.0 * d * w + w * w) / (d * d + w * (1.0 - 2.0 * d));
+}
+
+double orc_weno5_m_left(const double* f, double eps) {
+  double a = f[0], b = f[1], c = f[2], d = f[3], e = f[4];
+  double q0 = (2.0 * a - 7.0 * b + 11.0 * c) / 6.0;
+  double q1 = (-b + 5.0 * c + 2.0 * d) / 6.0;
+  double q2 = (2.0 * c + 5.0 * d - e) / 6.0;
+  double b0 = 13.0 / 12.0 * sq((a + c) - 2.0 * b) + 0.25 * sq((a + 3.0 * c) - 4.0 * b);
+  double b1 = 13.0 / 12.0 * sq((b + d) - 2.0 * c) + 0.25 * sq(b - d);
+  double b2 = 13.0 / 12.0 * sq((c + e) - 2.0 * d) + 0.25 * sq((3.0 * c + e) - 4.0 * d);
+  double a0 = 0.1 / sq(eps + b0);
+  double a1 = 0.6 / sq(eps + b1);
+  double a2 = 0.3 / sq(eps + b2);
+  double as = a0 + a1 + a2;
+  double m0 = orc_weno_m_map(a0 / as, 0.1);
+  double m1 = orc_weno_m_map(a1 / as, 0.6);
+  double m2 = orc_weno_m_map(a2 / as, 0.3);
+  return (m0 * q0 + m1 * q1 + m2 * q2) / (m0 + m1 + m2);
+}
+
+double orc_weno5_m_right(const double* f, double eps) {
+  double r[5] = {f[4], f[3], f[2], f[1], f[0]};
+  return orc_weno5_m_left(r, eps);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -423,6 +458,9 @@ static int face_flux(const orc_problem* P, const double* q, int d, const int idx
     } else if (P->weno_variant == 2) {
       WL[v] = orc_teno5_left(fl, P->weno_eps, ORC_TENO_CT);
       WR[v] = orc_teno5_right(fr, P->weno_eps, ORC_TENO_CT);
+    } else if (P->weno_variant == 3) {
+      WL[v] = orc_weno5_m_left(fl, P->weno_eps);
+      WR[v] = orc_weno5_m_right(fr, P->weno_eps);
     } else {
       WL[v] = orc_weno5_js_left(fl, P->weno_eps);
       WR[v] = orc_weno5_js_right(fr, P->weno_eps);

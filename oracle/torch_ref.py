@@ -209,6 +209,26 @@ def teno5_left(a, b, c, d, e, eps, ct=TENO_CT):
     return (w0 * q0 + w1 * q1 + w2 * q2) / (w0 + w1 + w2)
 
 
+def weno5_m_left(a, b, c, d, e, eps):
+    """WENO5-M (Sec. 3.2.1, Henrick-Aslam-Powers mapping of the JS weights)."""
+    q0 = (2.0 * a - 7.0 * b + 11.0 * c) / 6.0
+    q1 = (-b + 5.0 * c + 2.0 * d) / 6.0
+    q2 = (2.0 * c + 5.0 * d - e) / 6.0
+    b0 = 13.0 / 12.0 * ((a + c) - 2.0 * b) ** 2 + 0.25 * ((a + 3.0 * c) - 4.0 * b) ** 2
+    b1 = 13.0 / 12.0 * ((b + d) - 2.0 * c) ** 2 + 0.25 * (b - d) ** 2
+    b2 = 13.0 / 12.0 * ((c + e) - 2.0 * d) ** 2 + 0.25 * ((3.0 * c + e) - 4.0 * d) ** 2
+    a0 = torch.full_like(b0, 0.1) / (eps + b0) ** 2
+    a1 = torch.full_like(b1, 0.6) / (eps + b1) ** 2
+    a2 = torch.full_like(b2, 0.3) / (eps + b2) ** 2
+    s = a0 + a1 + a2
+
+    def g(w, dk):
+        return w * (dk + dk * dk - 3.0 * dk * w + w * w) / (dk * dk + w * (1.0 - 2.0 * dk))
+
+    m0, m1, m2 = g(a0 / s, 0.1), g(a1 / s, 0.6), g(a2 / s, 0.3)
+    return (m0 * q0 + m1 * q1 + m2 * q2) / (m0 + m1 + m2)
+
+
 def _min_first(a, b):
     return torch.where(a <= b, a, b)
 
@@ -285,7 +305,7 @@ def axis_contribution(P: Problem, q, d):
     # faces m - 1/2, m = 0..n; padded index of cell g is g + 3
     fl = [_sl(wp, ax, s, n + 1) for s in range(5)]       # centre m-1: cells m-3..m+1
     fr = [_sl(wp, ax, s + 1, n + 1) for s in range(5)]   # centre m: cells m-2..m+2
-    weno = {0: weno5_js_left, 1: weno5_z_left, 2: teno5_left}[P.weno_variant]
+    weno = {0: weno5_js_left, 1: weno5_z_left, 2: teno5_left, 3: weno5_m_left}[P.weno_variant]
     WL = weno(fl[0], fl[1], fl[2], fl[3], fl[4], P.eps)
     WR = weno(fr[4], fr[3], fr[2], fr[1], fr[0], P.eps)
     F, uf, _ = hllc(P, d, WL, WR)

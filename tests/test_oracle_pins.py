@@ -322,6 +322,88 @@ def test_teno_fifth_order_advection_convergence():
 
 
 # --------------------------------------------------------------------------
+# WENO5-M (Sec. 3.2.1: fifth order through the Henrick-Aslam-Powers mapping of
+# the JS weights)
+# --------------------------------------------------------------------------
+def test_weno_m_map_fixed_points_and_cubic_contact():
+    """With w = d + x the map is d + x^3 / (d (1 - d) + x (1 - 2 d)) (expand
+    the numerator: d^2 (1 - d) + x d (1 - 2 d) + x^3 over the denominator
+    d (1 - d) + x (1 - 2 d)): it fixes 0, d and 1, is flat to second order at
+    d, and increases on [0, 1].  A changed coefficient anywhere in the map
+    breaks one of these."""
+    for d in (0.1, 0.6, 0.3):
+        assert oracle.weno_m_map(0.0, d) == 0.0
+        assert abs(oracle.weno_m_map(1.0, d) - 1.0) <= 8 * ULP
+        assert abs(oracle.weno_m_map(d, d) - d) <= 4 * ULP
+        for x in (-d, -0.5 * d, -1e-3, 1e-4, 0.01, 0.2, 1.0 - d):
+            closed = d + x ** 3 / (d * (1.0 - d) + x * (1.0 - 2.0 * d))
+            assert abs(oracle.weno_m_map(d + x, d) - closed) <= 16 * ULP, (d, x)
+        ws = np.linspace(0.0, 1.0, 1001)
+        g = np.array([oracle.weno_m_map(w, d) for w in ws])
+        assert np.all(np.diff(g) > 0)
+        # slope (1 + d)/d at 0: small weights are enlarged, not suppressed
+        assert abs(oracle.weno_m_map(1e-9, d) / 1e-9 - (1.0 + d) / d) <= 1e-6
+
+
+def test_weno_m_linear_limit_quadratics_and_step():
+    rng = np.random.default_rng(31)
+    h = 0.05
+    for _ in range(5):
+        coef = rng.normal(size=5)
+        f = np.array([_avg_poly(coef, (k - 2.5) * h, (k - 1.5) * h) for k in range(5)])
+        # eps -> infinity: JS weights are the linear ones, a fixed point of the map
+        assert abs(oracle.weno5_m_left(f, eps=1e30) - _linear5(f)) <= 1e-13 * (1 + abs(_linear5(f)))
+        assert abs(oracle.weno5_m_right(f, eps=1e30) - _linear5(f[::-1].copy())) <= 1e-13 * (1 + np.abs(f).max())
+    for _ in range(5):
+        coef = rng.normal(size=3)
+        f = np.array([_avg_poly(coef, (k - 2.5) * 0.1, (k - 1.5) * 0.1) for k in range(5)])
+        exact = sum(ck * 0.05 ** k for k, ck in enumerate(coef))
+        assert abs(oracle.weno5_m_left(f) - exact) <= 1e-13 * (1 + abs(exact))
+    # a step: the smooth stencil dominates; the mapped weights of the rough
+    # stencils are (1 + d)/d times the JS ones, still ~1e-11
+    v = oracle.weno5_m_left(np.array([0.0, 0.0, 0.0, 1.0, 1.0]))
+    vj = oracle.weno5_js_left(np.array([0.0, 0.0, 0.0, 1.0, 1.0]))
+    assert 0.0 < vj < v < 1e-10
+    v = oracle.weno5_m_left(np.array([0.0, 0.0, 1.0, 1.0, 1.0]))
+    assert abs(v - 1.0) < 1e-10
+
+
+def test_weno_m_recovers_the_linear_scheme_at_a_critical_point():
+    """Cell averages of 2 + cos x with the extremum at the face: the JS weights
+    depart from the linear ones and its error is 7-10x that of the linear
+    scheme, while the mapped weights give the linear scheme's error (the
+    reason the paper gives for the mapping: fifth order kept at critical
+    points)."""
+    for h in (0.2, 0.1, 0.05, 0.025):
+        for off in (0.0, 0.3):
+            xs = (np.arange(5) - 2) * h + off * h
+            f = np.array([(np.sin(x + h / 2) - np.sin(x - h / 2)) / h for x in xs]) + 2.0
+            exact = np.cos(xs[2] + h / 2) + 2.0
+            e_lin = abs(_linear5(f) - exact)
+            e_m = abs(oracle.weno5_m_left(f, eps=1e-40) - exact)
+            e_js = abs(oracle.weno5_js_left(f, eps=1e-40) - exact)
+            assert abs(e_m - e_lin) <= 0.05 * e_lin + 1e-14, (h, off, e_m, e_lin)
+            assert e_js >= 5 * e_lin, (h, off, e_js, e_lin)
+
+
+def test_weno_m_fifth_order_advection_convergence():
+    """The paper's convergence problem (Sec. 3.5) with the mapped weights."""
+    errs = []
+    for N in (16, 32, 64):
+        c = W.advection_1d(N, amplitude=0.25, gamma2=1.6)
+        c.weno_variant = 3
+        O = oracle.Oracle(c)
+        q = O.prim_to_cons(c.w)
+        T, h = 5.0, 1.0 / N
+        ns = int(np.ceil(T / (0.25 * h ** (5.0 / 3.0))))
+        O.run(q, ns, dt_fixed=T / ns)
+        ex = W.advection_exact_average(N, 0.25, T)
+        errs.append(np.sqrt(np.mean((q[4, 0, 0] - ex) ** 2)))
+    orders = np.log2(np.array(errs[:-1]) / np.array(errs[1:]))
+    assert orders[-1] >= 4.5, orders
+
+
+# --------------------------------------------------------------------------
 # C-5: HLLC
 # --------------------------------------------------------------------------
 def _prim_state(rng, nf=2, D=3, speed=100.0):
@@ -519,7 +601,7 @@ def test_rhs_cells_matches_full_rhs_bitwise():
                                          (3, (12, 10, 9), 2, (1, 2, 0)), (1, (30,), 2, (2,))])
 def test_independent_torch_implementation_agrees_bitwise(nd, n, nf, bc):
     """The whole-array torch version (independent code) reproduces the oracle bit for bit."""
-    for variant in (0, 1, 2):
+    for variant in (0, 1, 2, 3):
         _torch_agrees(nd, n, nf, bc, variant)
 
 
