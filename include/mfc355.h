@@ -73,13 +73,17 @@ enum { MFC_FP64 = 0, MFC_FP32_MIXED = 1 };
 /* Reconstruction weights, all on the same three candidates, smoothness
  * indicators, linear weights d_k and eps:
  *   MFC_WENO_JS  Jiang-Shu, d_k/(eps + beta_k)^2 (Sec. 3.2.1);
+ *   MFC_WENO_M   the Jiang-Shu weights w_k mapped by Henrick, Aslam and
+ *                Powers' g_k(w) = w (d_k + d_k^2 - 3 d_k w + w^2) /
+ *                (d_k^2 + w (1 - 2 d_k)) and normalized again (Sec. 3.2.1,
+ *                which names the mapping without printing it);
  *   MFC_WENO_Z   d_k (1 + tau/(beta_k + eps)), tau = |beta_0 - beta_2|, q = 1
  *                (Sec. 4.2.2);
  *   MFC_TENO     stencil k kept when its share of gamma_k =
  *                d_k (1 + tau/(beta_k + eps))^6 reaches C_T = 1e-5, kept
  *                stencils weighted d_k (Sec. 4.2.2; the cut-off is not printed
  *                there: the published fifth-order value). */
-enum { MFC_WENO_JS = 0, MFC_WENO_Z = 1, MFC_TENO = 2 };
+enum { MFC_WENO_JS = 0, MFC_WENO_Z = 1, MFC_TENO = 2, MFC_WENO_M = 3 };
 
 typedef struct {
   int32_t abi_version; /* must equal MFC_ABI_VERSION */
@@ -94,7 +98,7 @@ typedef struct {
   double gamma[2];     /* stiffened-gas gamma_i > 1 per fluid (Sec. 2.2) */
   double pi_inf[2];    /* stiffened-gas pi_inf,i >= 0 per fluid */
   double weno_eps;     /* WENO smoothness regularization, > 0 (1e-6) */
-  int32_t weno_variant; /* MFC_WENO_JS, MFC_WENO_Z or MFC_TENO */
+  int32_t weno_variant; /* MFC_WENO_JS, MFC_WENO_Z, MFC_TENO or MFC_WENO_M */
 } mfc_problem;
 
 typedef struct mfc_ctx mfc_ctx;

@@ -14,7 +14,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libmfc355.so")
 
 MFC_ABI_VERSION = 2
-MFC_WENO_JS, MFC_WENO_Z, MFC_TENO = 0, 1, 2
+MFC_WENO_JS, MFC_WENO_Z, MFC_TENO, MFC_WENO_M = 0, 1, 2, 3
 MFC_OK, MFC_ERR_ARG, MFC_ERR_SHAPE, MFC_ERR_UNSUPPORTED = 0, -1, -2, -3
 MFC_ERR_HIP, MFC_ERR_NONFINITE, MFC_ERR_ALLOC = -4, -5, -6
 MFC_BC_PERIODIC, MFC_BC_EXTRAP, MFC_BC_SLIPWALL = 0, 1, 2

@@ -197,6 +197,78 @@ __host__ __device__ __forceinline__ void weno_z_left_vjp(double a, double b, dou
   g[4] += gD3;
 }
 
+// Adjoint of the left-biased WENO5-M value (mapped JS weights, Sec. 3.2.1).
+// Forward: JS weights w_k = n_k/N (n_k = d_k prod_{j != k} s_j^2), mapped
+// h_k = g_k(w_k) = num_k/den_k, weights W_k = h_k / sum h, y = c + sum W_k l_k/6.
+// Cotangents: of h_k, gy (l_k/6 - (y - c)) / sum h; of w_k, that times
+// g_k'(w_k) = (num_k' den_k - num_k (1 - 2 d_k)) / den_k^2 with num_k' =
+// d_k + d_k^2 - 6 d_k w_k + 3 w_k^2; of s_k, -2 w_k (wbar_k - sum_j wbar_j w_j)/s_k
+// (the JS normalization), then as in weno_left_vjp.  Accumulates g[0..4].
+__host__ __device__ __forceinline__ void weno_m_left_vjp(double a, double b, double c, double d, double e,
+                                                         double eps, double gy, double* g) {
+  const double D0 = b - a, D1 = c - b, D2 = d - c, D3 = e - d;
+  const double u0 = D1 - D0, v0 = 3.0 * D1 - D0;
+  const double u1 = D2 - D1, v1 = D1 + D2;
+  const double u2 = D3 - D2, v2 = D3 - 3.0 * D2;
+  const double e4 = 4.0 * eps;
+  const double s0 = e4 + ((13.0 / 3.0) * u0 * u0 + v0 * v0);
+  const double s1 = e4 + ((13.0 / 3.0) * u1 * u1 + v1 * v1);
+  const double s2 = e4 + ((13.0 / 3.0) * u2 * u2 + v2 * v2);
+  const double m0 = s1 * s2, m1 = s0 * s2, m2 = s0 * s1;   // prod_{j != k} s_j
+  const double n0 = 0.1 * (m0 * m0), n1 = 0.6 * (m1 * m1), n2 = 0.3 * (m2 * m2);
+  const double N = n0 + n1 + n2;
+  const double P = s0 * m0;
+  const double inv = fast_rcp(N * P);
+  const double rN = P * inv;    // 1/N
+  const double rP = N * inv;    // 1/(s0 s1 s2)
+  const double w0 = n0 * rN, w1 = n1 * rN, w2 = n2 * rN;
+  double num0, den0, num1, den1, num2, den2;
+  weno_m_map(w0, 0.1, num0, den0);
+  weno_m_map(w1, 0.6, num1, den1);
+  weno_m_map(w2, 0.3, num2, den2);
+  const double c0 = den1 * den2, c1 = den0 * den2, c2 = den0 * den1;   // prod_{j != k} den_j
+  const double E0 = num0 * c0, E1 = num1 * c1, E2 = num2 * c2;
+  const double H = E0 + E1 + E2;
+  const double Q = den0 * c0;
+  const double inv2 = fast_rcp(H * Q);
+  const double rH = Q * inv2;   // 1/H
+  const double rQ = H * inv2;   // 1/(den0 den1 den2)
+  const double W0 = E0 * rH, W1 = E1 * rH, W2 = E2 * rH;
+  const double l0 = 5.0 * D1 - 2.0 * D0, l1 = D1 + 2.0 * D2, l2 = 4.0 * D2 - D3;
+  const double k6 = 1.0 / 6.0;
+  const double dy = (W0 * l0 + W1 * l1 + W2 * l2) * k6;
+  const double gk = gy * k6;
+  const double gl0 = gk * W0, gl1 = gk * W1, gl2 = gk * W2;
+  // cotangents of the mapped values h_k = num_k/den_k: 1/sum h = Q/H
+  const double gh = gy * (Q * rH);
+  const double gh0 = gh * (l0 * k6 - dy), gh1 = gh * (l1 * k6 - dy), gh2 = gh * (l2 * k6 - dy);
+  // of the JS weights through the map (1/den_k = c_k / Q)
+  const double id0 = c0 * rQ, id1 = c1 * rQ, id2 = c2 * rQ;
+  const double dn0 = (0.1 + 0.01) + w0 * (3.0 * w0 - 0.6);
+  const double dn1 = (0.6 + 0.36) + w1 * (3.0 * w1 - 3.6);
+  const double dn2 = (0.3 + 0.09) + w2 * (3.0 * w2 - 1.8);
+  const double gw0 = gh0 * ((dn0 - num0 * (0.8 * id0)) * id0);
+  const double gw1 = gh1 * ((dn1 - num1 * (-0.2 * id1)) * id1);
+  const double gw2 = gh2 * ((dn2 - num2 * (0.4 * id2)) * id2);
+  const double cw = gw0 * w0 + gw1 * w1 + gw2 * w2;
+  // of s_k through the JS normalization (1/s_k = m_k / (s0 s1 s2))
+  const double gs0 = -2.0 * w0 * (gw0 - cw) * (m0 * rP);
+  const double gs1 = -2.0 * w1 * (gw1 - cw) * (m1 * rP);
+  const double gs2 = -2.0 * w2 * (gw2 - cw) * (m2 * rP);
+  const double gu0 = gs0 * (26.0 / 3.0) * u0, gv0 = gs0 * 2.0 * v0;
+  const double gu1 = gs1 * (26.0 / 3.0) * u1, gv1 = gs1 * 2.0 * v1;
+  const double gu2 = gs2 * (26.0 / 3.0) * u2, gv2 = gs2 * 2.0 * v2;
+  const double gD0 = -2.0 * gl0 - gu0 - gv0;
+  const double gD1 = 5.0 * gl0 + gl1 + gu0 + 3.0 * gv0 - gu1 + gv1;
+  const double gD2 = 2.0 * gl1 + 4.0 * gl2 + gu1 + gv1 - gu2 - 3.0 * gv2;
+  const double gD3 = -gl2 + gu2 + gv2;
+  g[0] -= gD0;
+  g[1] += gD0 - gD1;
+  g[2] += gy + gD1 - gD2;
+  g[3] += gD2 - gD3;
+  g[4] += gD3;
+}
+
 // Adjoint of the left-biased TENO5 value (Sec. 4.2.2): the kept set is decided
 // exactly as in the forward reconstruction and the weights are then constant,
 // so y = c + sum_k w_k l_k / 6 with w_k = d_k delta_k / sum d delta is linear

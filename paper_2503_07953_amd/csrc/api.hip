@@ -258,7 +258,7 @@ int mfc_validate(const mfc_problem* p) {
   for (int i = 0; i < p->num_fluids; ++i)
     if (!(p->gamma[i] > 1.0) || !(p->pi_inf[i] >= 0.0) || !(p->pi_inf[i] < 1e300)) return MFC_ERR_ARG;
   if (!(p->weno_eps > 0.0)) return MFC_ERR_ARG;
-  if (p->weno_variant < MFC_WENO_JS || p->weno_variant > MFC_TENO) return MFC_ERR_UNSUPPORTED;
+  if (p->weno_variant < MFC_WENO_JS || p->weno_variant > MFC_WENO_M) return MFC_ERR_UNSUPPORTED;
   return MFC_OK;
 }
 

@@ -325,8 +325,96 @@ __device__ __forceinline__ void teno5(float a, float b, float c, float d, float 
   fr = c + (wr0 * r0 + wr1 * r1 + wr2 * r2) * __builtin_amdgcn_rcpf(6.0f * (wr0 + wr1 + wr2));
 }
 
+// WENO5-M (Sec. 3.2.1: fifth order kept by the mapped weights of Henrick,
+// Aslam and Powers).  The JS weights w_k of weno5_js, normalized, are mapped by
+//   g_k(w) = w (d_k + d_k^2 - 3 d_k w + w^2) / (d_k^2 + w (1 - 2 d_k))
+// and normalized again.  Mapped weight k is N_k/Q_k with Q_k >= d_k min(d_k,
+// 1 - d_k) > 0 on [0, 1]; over the common denominator Q_0 Q_1 Q_2 each side's
+// normalization is one sum, so one refined reciprocal serves the JS
+// normalization of both sides and one the mapped normalization of both.
+__host__ __device__ __forceinline__ void weno_m_map(double w, double dk, double& num, double& den) {
+  num = w * ((dk + dk * dk) + w * (w - 3.0 * dk));
+  den = dk * dk + w * (1.0 - 2.0 * dk);
+}
+
+__host__ __device__ __forceinline__ void weno5_m(double a, double b, double c, double d, double e, double eps,
+                                                 double& fl, double& fr) {
+  const double D0 = b - a, D1 = c - b, D2 = d - c, D3 = e - d;
+  const double u0 = D1 - D0, v0 = 3.0 * D1 - D0;
+  const double u1 = D2 - D1, v1 = D1 + D2;
+  const double u2 = D3 - D2, v2 = D3 - 3.0 * D2;
+  const double e4 = 4.0 * eps;
+  const double s0 = e4 + ((13.0 / 3.0) * u0 * u0 + v0 * v0);
+  const double s1 = e4 + ((13.0 / 3.0) * u1 * u1 + v1 * v1);
+  const double s2 = e4 + ((13.0 / 3.0) * u2 * u2 + v2 * v2);
+  const double t0 = s0 * s0, t1 = s1 * s1, t2 = s2 * s2;
+  const double p0 = t1 * t2, p1 = t0 * t2, p2 = t0 * t1;
+  const double w1 = 0.6 * p1;
+  const double wl0 = 0.1 * p0, wl2 = 0.3 * p2;
+  const double wr0 = 0.1 * p2, wr2 = 0.3 * p0;
+  const double dl = wl0 + w1 + wl2;
+  const double dr = wr0 + w1 + wr2;
+  const double inv = fast_rcp(dl * dr);
+  const double idl = dr * inv, idr = dl * inv;
+  // left: d = (0.1, 0.6, 0.3) on candidates l0, l1, l2; right: the mirror
+  double nl0, ql0, nl1, ql1, nl2, ql2, nr0, qr0, nr1, qr1, nr2, qr2;
+  weno_m_map(wl0 * idl, 0.1, nl0, ql0);
+  weno_m_map(w1 * idl, 0.6, nl1, ql1);
+  weno_m_map(wl2 * idl, 0.3, nl2, ql2);
+  weno_m_map(wr0 * idr, 0.1, nr0, qr0);
+  weno_m_map(w1 * idr, 0.6, nr1, qr1);
+  weno_m_map(wr2 * idr, 0.3, nr2, qr2);
+  const double el0 = nl0 * (ql1 * ql2), el1 = nl1 * (ql0 * ql2), el2 = nl2 * (ql0 * ql1);
+  const double er0 = nr0 * (qr1 * qr2), er1 = nr1 * (qr0 * qr2), er2 = nr2 * (qr0 * qr1);
+  const double hl = el0 + el1 + el2, hr = er0 + er1 + er2;
+  const double l0 = 5.0 * D1 - 2.0 * D0, l1 = D1 + 2.0 * D2, l2 = 4.0 * D2 - D3;
+  const double r0 = 2.0 * D3 - 5.0 * D2, r1 = -(D2 + 2.0 * D1), r2 = D0 - 4.0 * D1;
+  const double inv2 = fast_rcp(6.0 * (hl * hr));
+  fl = c + (el0 * l0 + el1 * l1 + el2 * l2) * (hr * inv2);
+  fr = c + (er0 * r0 + er1 * r1 + er2 * r2) * (hl * inv2);
+}
+
+// FP32 WENO5-M: the JS weights of the float weno5_js (hardware reciprocals of
+// t_k), normalized, mapped in float and normalized per side.
+__device__ __forceinline__ void weno5_m(float a, float b, float c, float d, float e, float eps, float& fl,
+                                        float& fr) {
+  const float D0 = b - a, D1 = c - b, D2 = d - c, D3 = e - d;
+  const float u0 = D1 - D0, v0 = 3.0f * D1 - D0;
+  const float u1 = D2 - D1, v1 = D1 + D2;
+  const float u2 = D3 - D2, v2 = D3 - 3.0f * D2;
+  const float e4 = 4.0f * eps;
+  const float s0 = e4 + ((13.0f / 3.0f) * u0 * u0 + v0 * v0);
+  const float s1 = e4 + ((13.0f / 3.0f) * u1 * u1 + v1 * v1);
+  const float s2 = e4 + ((13.0f / 3.0f) * u2 * u2 + v2 * v2);
+  const float a0 = __builtin_amdgcn_rcpf(s0 * s0);
+  const float a1 = __builtin_amdgcn_rcpf(s1 * s1);
+  const float a2 = __builtin_amdgcn_rcpf(s2 * s2);
+  const float w1 = 0.6f * a1;
+  const float wl0 = 0.1f * a0, wl2 = 0.3f * a2;
+  const float wr0 = 0.1f * a2, wr2 = 0.3f * a0;
+  const float idl = __builtin_amdgcn_rcpf(wl0 + w1 + wl2);
+  const float idr = __builtin_amdgcn_rcpf(wr0 + w1 + wr2);
+  auto map = [](float w, float dk, float& num, float& den) {
+    num = w * ((dk + dk * dk) + w * (w - 3.0f * dk));
+    den = dk * dk + w * (1.0f - 2.0f * dk);
+  };
+  float nl0, ql0, nl1, ql1, nl2, ql2, nr0, qr0, nr1, qr1, nr2, qr2;
+  map(wl0 * idl, 0.1f, nl0, ql0);
+  map(w1 * idl, 0.6f, nl1, ql1);
+  map(wl2 * idl, 0.3f, nl2, ql2);
+  map(wr0 * idr, 0.1f, nr0, qr0);
+  map(w1 * idr, 0.6f, nr1, qr1);
+  map(wr2 * idr, 0.3f, nr2, qr2);
+  const float el0 = nl0 * (ql1 * ql2), el1 = nl1 * (ql0 * ql2), el2 = nl2 * (ql0 * ql1);
+  const float er0 = nr0 * (qr1 * qr2), er1 = nr1 * (qr0 * qr2), er2 = nr2 * (qr0 * qr1);
+  const float l0 = 5.0f * D1 - 2.0f * D0, l1 = D1 + 2.0f * D2, l2 = 4.0f * D2 - D3;
+  const float r0 = 2.0f * D3 - 5.0f * D2, r1 = -(D2 + 2.0f * D1), r2 = D0 - 4.0f * D1;
+  fl = c + (el0 * l0 + el1 * l1 + el2 * l2) * __builtin_amdgcn_rcpf(6.0f * (el0 + el1 + el2));
+  fr = c + (er0 * r0 + er1 * r1 + er2 * r2) * __builtin_amdgcn_rcpf(6.0f * (er0 + er1 + er2));
+}
+
 // The reconstruction of a kernel instantiation: WV = 0 WENO5-JS, 1 WENO5-Z,
-// 2 TENO5.  (A compile-time choice: a run-time branch inside the unrolled row
+// 2 TENO5, 3 WENO5-M.  (A compile-time choice: a run-time branch inside the unrolled row
 // loops would make every kernel hold the registers of all of them.)
 template <int WV, typename T>
 __device__ __forceinline__ void weno5(T a, T b, T c, T d, T e, T eps, T& fl, T& fr) {
@@ -334,6 +422,8 @@ __device__ __forceinline__ void weno5(T a, T b, T c, T d, T e, T eps, T& fl, T& 
     weno5_z(a, b, c, d, e, eps, fl, fr);
   else if constexpr (WV == 2)
     teno5(a, b, c, d, e, eps, fl, fr);
+  else if constexpr (WV == 3)
+    weno5_m(a, b, c, d, e, eps, fl, fr);
   else
     weno5_js(a, b, c, d, e, eps, fl, fr);
 }

@@ -279,6 +279,7 @@ hipError_t launch_rhs(int nf, int ndim, const Params& pm, const Real* qk, Real* 
   if (nf == NF && ndim == D)                                                                   \
     return pm.weno_variant == 1   ? launch_rhs_t<NF, D, Real, 1>(pm, qk, acc, qn, qout, st, final_step, flag, s, tm) \
            : pm.weno_variant == 2 ? launch_rhs_t<NF, D, Real, 2>(pm, qk, acc, qn, qout, st, final_step, flag, s, tm) \
+           : pm.weno_variant == 3 ? launch_rhs_t<NF, D, Real, 3>(pm, qk, acc, qn, qout, st, final_step, flag, s, tm) \
                                   : launch_rhs_t<NF, D, Real, 0>(pm, qk, acc, qn, qout, st, final_step, flag, s, tm);
   MFC_CASE(1, 1)
   MFC_CASE(1, 2)

@@ -214,6 +214,9 @@ __device__ __forceinline__ void face_tile(const Params pm, const double* __restr
     } else if constexpr (WV == 2) {
       teno_left_vjp(Ws(0, v), Ws(1, v), Ws(2, v), Ws(3, v), Ws(4, v), pm.eps, WLb[v], g);
       teno_left_vjp(Ws(5, v), Ws(4, v), Ws(3, v), Ws(2, v), Ws(1, v), pm.eps, WRb[v], gr);
+    } else if constexpr (WV == 3) {
+      weno_m_left_vjp(Ws(0, v), Ws(1, v), Ws(2, v), Ws(3, v), Ws(4, v), pm.eps, WLb[v], g);
+      weno_m_left_vjp(Ws(5, v), Ws(4, v), Ws(3, v), Ws(2, v), Ws(1, v), pm.eps, WRb[v], gr);
     } else {
       weno_left_vjp(Ws(0, v), Ws(1, v), Ws(2, v), Ws(3, v), Ws(4, v), pm.eps, WLb[v], g);
       weno_left_vjp(Ws(5, v), Ws(4, v), Ws(3, v), Ws(2, v), Ws(1, v), pm.eps, WRb[v], gr);
@@ -443,6 +446,7 @@ hipError_t launch_rhs_vjp(int nf, int ndim, const Params& pm, const double* q, c
   if (nf == NF && ndim == D)                                                              \
     return pm.weno_variant == 1   ? launch_rhs_vjp_t<NF, D, 1>(pm, q, rbar, qbar, sc, accumulate, s, tm) \
            : pm.weno_variant == 2 ? launch_rhs_vjp_t<NF, D, 2>(pm, q, rbar, qbar, sc, accumulate, s, tm) \
+           : pm.weno_variant == 3 ? launch_rhs_vjp_t<NF, D, 3>(pm, q, rbar, qbar, sc, accumulate, s, tm) \
                                   : launch_rhs_vjp_t<NF, D, 0>(pm, q, rbar, qbar, sc, accumulate, s, tm);
   MFC_CASE(1, 1)
   MFC_CASE(1, 2)

@@ -68,7 +68,8 @@ def test_num_eqs(L):
     (dict(weno_eps=0.0), -1),
     (dict(weno_variant=1), 0),
     (dict(weno_variant=2), 0),
-    (dict(weno_variant=3), -3),
+    (dict(weno_variant=3), 0),
+    (dict(weno_variant=4), -3),
     (dict(weno_variant=-1), -3),
 ])
 def test_validation_codes(L, kw, code):

@@ -46,9 +46,10 @@ CASES = [
 
 
 @pytest.mark.parametrize("nd,n,nf,bc,variant", [cs + (0,) for cs in CASES]
-                         + [CASES[2] + (1,), CASES[5] + (1,), CASES[2] + (2,), CASES[5] + (2,)])
+                         + [CASES[2] + (1,), CASES[5] + (1,), CASES[2] + (2,), CASES[5] + (2,),
+                            CASES[2] + (3,), CASES[5] + (3,), CASES[4] + (3,)])
 def test_rhs_vjp_matches_reference_autograd(nd, n, nf, bc, variant):
-    """variant 0: WENO5-JS, 1: WENO5-Z, 2: TENO5."""
+    """variant 0: WENO5-JS, 1: WENO5-Z, 2: TENO5, 3: WENO5-M."""
     _say("rhs_vjp", nd, n, nf, bc, "variant", variant)
     c = W.random_case(nd, n, nf=nf, seed=40 + nd, bc=bc, speed=300.0 if nf == 1 else 150.0)
     c.weno_variant = variant

@@ -156,9 +156,11 @@ def _variant_steps_match(c, nf, nd, flux_scale=False):
 
 
 @pytest.mark.parametrize("nd,n,nf,bc,variant", [CASES[0] + (1,), CASES[3] + (1,), CASES[6] + (1,), CASES[7] + (1,),
-                                                CASES[0] + (2,), CASES[7] + (2,)])
+                                                CASES[0] + (2,), CASES[7] + (2,),
+                                                CASES[0] + (3,), CASES[3] + (3,), CASES[6] + (3,), CASES[7] + (3,)])
 def test_weno_variants_rhs_and_steps_match_oracle(nd, n, nf, bc, variant):
-    """WENO5-Z (1) and TENO5 (2) of Sec. 4.2.2 through the same kernels, on
+    """WENO5-Z (1), TENO5 (2) of Sec. 4.2.2 and WENO5-M (3, the mapped
+    weights of Sec. 3.2.1) through the same kernels, on
     white-noise states.  TENO5 is run on the one-fluid ones only: on two-fluid
     white noise its three stencils are equally rough, it keeps all of them and
     the linear five-point scheme makes negative face densities across the
@@ -169,7 +171,7 @@ def test_weno_variants_rhs_and_steps_match_oracle(nd, n, nf, bc, variant):
     _variant_steps_match(c, nf, nd)
 
 
-@pytest.mark.parametrize("variant", [1, 2])
+@pytest.mark.parametrize("variant", [1, 2, 3])
 @pytest.mark.parametrize("name", ["shock-cylinder-96", "bubble-cloud-64"])
 def test_weno_variants_two_fluid_flows_match_oracle(name, variant):
     """The variants on the two-fluid flows of the benchmarks at small size."""
@@ -206,18 +208,18 @@ def test_teno_rough_two_fluid_flagged_on_both_sides():
 
 
 def test_weno_variants_differ():
-    """The three reconstructions are distinct code paths (a non-smooth state)."""
+    """The four reconstructions are distinct code paths (a non-smooth state)."""
     c = W.random_case(2, (40, 30), nf=2, seed=9, bc=(W.EXTRAP, W.PERIODIC))
     O = oracle.Oracle(c)
     q = O.prim_to_cons(c.w)
     rs = []
-    for variant in (0, 1, 2):
+    for variant in (0, 1, 2, 3):
         c.weno_variant = variant
         S = _solver(c)
         rs.append(S.rhs(S.to_device(q)).cpu().numpy())
-    assert not np.array_equal(rs[0], rs[1])
-    assert not np.array_equal(rs[0], rs[2])
-    assert not np.array_equal(rs[1], rs[2])
+    for i in range(4):
+        for j in range(i + 1, 4):
+            assert not np.array_equal(rs[i], rs[j]), (i, j)
 
 
 def test_sod_full_run_matches_oracle_and_exact():
