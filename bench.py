@@ -35,17 +35,19 @@ def log(*a):
 def pass_bytes_per_cell(kind, neq, esize, ndim, stage_mix=(1, 1, 1)):
     """Algorithmic HBM bytes per cell of one launch of a pass kind.
 
-    x pass writes the RHS accumulator (read q, write acc); middle passes read
-    and write it; the last pass reads q_k, acc and (stages 2 and 3) q^n and
-    writes the next stage state; the signal reduction reads q once.
+    The passes of a stage run z, y, x (from the highest axis down): the first
+    writes the RHS accumulator (read q, write acc), a middle one reads and
+    writes it, and the x pass, last, reads q_k, acc and (stages 2 and 3) q^n
+    and writes the next stage state.  In 1D the x pass is alone: q_k, q^n,
+    next state.  The signal reduction reads q once.
     """
-    last = {1: "pass_x", 2: "pass_y", 3: "pass_z"}[ndim]
+    first = {1: "pass_x", 2: "pass_y", 3: "pass_z"}[ndim]
+    reads_qn = (0 + 1 + 1) / 3.0
     if kind == "signal":
         return neq * esize
-    if kind == last:
-        reads_qn = (0 + 1 + 1) / 3.0
-        return (3 + reads_qn) * neq * esize
     if kind == "pass_x":
+        return ((2 if ndim == 1 else 3) + reads_qn) * neq * esize
+    if kind == first:
         return 2 * neq * esize
     return 3 * neq * esize
 

@@ -55,7 +55,7 @@ __global__ __launch_bounds__((Tile<DIR, D, Real>::NT)) void sweep_kernel(Params 
                                                                  Real* __restrict__ acc,
                                                                  const Real* __restrict__ qn,
                                                                  Real* __restrict__ qout, StageArgs st,
-                                                                 int* __restrict__ flag) {
+                                                                 int* __restrict__ flag, long long block_base) {
   using R = Rows<NF, D>;
   using TL = Tile<DIR, D, Real>;
   constexpr int NEQ = R::NEQ;
@@ -68,7 +68,26 @@ __global__ __launch_bounds__((Tile<DIR, D, Real>::NT)) void sweep_kernel(Params 
 
   // tile origin (first output cell along DIR) and the fixed coordinates
   int a, b, org, cx = 0, cy = 0, cz = 0;
-  if constexpr (DIR == 0) {
+  if constexpr (DIR == 0 && D > 1) {
+    // One-dimensional grid.  Blocks are dispatched to the eight XCDs in turn
+    // (block L to XCD L mod 8); XCD k takes the x tiles of row group
+    // 8 g + k in order (g = (L / 8) / tiles per row), so neighbouring x tiles,
+    // which share the 128-byte lines at their edges and their halo, run on
+    // one XCD one after the other, while the eight XCDs work on adjacent
+    // row groups at any time.
+    a = threadIdx.x;
+    b = threadIdx.y;
+    const long long ntx = (nx + TL::OUT - 1) / TL::OUT;
+    const long long nrg_y = (ny + TL::TB - 1) / TL::TB;
+    const long long L = block_base + blockIdx.x;  // launches come in chunks that start at multiples of 8
+    const long long j = L >> 3;
+    const long long g = j / ntx;
+    const long long rg = g * 8 + (L & 7);
+    if (rg >= nrg_y * pm.n[2]) return;  // padding blocks of the last group of eight
+    org = (int)(j - g * ntx) * TL::OUT;
+    cz = (int)(rg / nrg_y);
+    cy = (int)(rg - cz * nrg_y) * TL::TB;  // + line
+  } else if constexpr (DIR == 0) {
     a = threadIdx.x;
     b = threadIdx.y;
     org = blockIdx.x * TL::OUT;
@@ -229,7 +248,25 @@ static hipError_t launch_one(const Params& pm, const Real* qk, Real* acc, const 
   using TL = Tile<DIR, D, Real>;
   dim3 block, grid;
   const int nx = pm.n[0], ny = pm.n[1], nz = pm.n[2];
-  if constexpr (DIR == 0) {
+  if constexpr (DIR == 0 && D > 1) {
+    // x tiles over groups of eight row groups, launched in chunks of at most
+    // 2^24 blocks (64 x 2^24 work-items along x stays below 2^32); every chunk
+    // starts at a multiple of 8 so that block L keeps XCD L mod 8
+    block = dim3(TL::TA, TL::TB, 1);
+    const long long groups = (long long)((ny + TL::TB - 1) / TL::TB) * nz;
+    const long long total = (long long)((nx + TL::OUT - 1) / TL::OUT) * ((groups + 7) / 8) * 8;
+    constexpr long long kChunk = 1ll << 24;
+    hipError_t e = hipSuccess;
+    if (tm) tm->begin(KIND_PASS_X, s);
+    for (long long base = 0; base < total && e == hipSuccess; base += kChunk) {
+      const long long nb = (total - base < kChunk) ? total - base : kChunk;
+      hipLaunchKernelGGL((sweep_kernel<NF, D, DIR, Real, MODE, WV>), dim3((unsigned)nb, 1, 1), block, 0, s, pm, qk,
+                         acc, qn, qout, st, flag, base);
+      e = hipGetLastError();
+    }
+    if (tm) tm->end(KIND_PASS_X, s);
+    return e;
+  } else if constexpr (DIR == 0) {
     block = dim3(TL::TA, TL::TB, 1);
     grid = dim3((nx + TL::OUT - 1) / TL::OUT, (ny + TL::TB - 1) / TL::TB, nz);
   } else if constexpr (DIR == 1) {
@@ -241,7 +278,7 @@ static hipError_t launch_one(const Params& pm, const Real* qk, Real* acc, const 
   }
   if (tm) tm->begin(KIND_PASS_X + DIR, s);
   hipLaunchKernelGGL((sweep_kernel<NF, D, DIR, Real, MODE, WV>), grid, block, 0, s, pm, qk, acc, qn, qout, st,
-                     flag);
+                     flag, 0ll);
   if (tm) tm->end(KIND_PASS_X + DIR, s);
   return hipGetLastError();
 }
@@ -257,17 +294,17 @@ static hipError_t launch_rhs_t(const Params& pm, const Real* qk, Real* acc, cons
     else
       e = launch_one<NF, D, 0, Real, MODE_WRITE, WV>(pm, qk, acc, qn, qout, st, flag, s, tm);
   } else {
-    e = launch_one<NF, D, 0, Real, MODE_WRITE, WV>(pm, qk, acc, qn, qout, st, flag, s, tm);
+    constexpr int FIRST = D - 1;
+    e = launch_one<NF, D, FIRST, Real, MODE_WRITE, WV>(pm, qk, acc, qn, qout, st, flag, s, tm);
     if (e != hipSuccess) return e;
     if constexpr (D == 3) {
       e = launch_one<NF, D, 1, Real, MODE_ACC, WV>(pm, qk, acc, qn, qout, st, flag, s, tm);
       if (e != hipSuccess) return e;
     }
-    constexpr int LAST = D - 1;
     if (final_step)
-      e = launch_one<NF, D, LAST, Real, MODE_ACC | MODE_STEP, WV>(pm, qk, acc, qn, qout, st, flag, s, tm);
+      e = launch_one<NF, D, 0, Real, MODE_ACC | MODE_STEP, WV>(pm, qk, acc, qn, qout, st, flag, s, tm);
     else
-      e = launch_one<NF, D, LAST, Real, MODE_ACC, WV>(pm, qk, acc, qn, qout, st, flag, s, tm);
+      e = launch_one<NF, D, 0, Real, MODE_ACC, WV>(pm, qk, acc, qn, qout, st, flag, s, tm);
   }
   return e;
 }

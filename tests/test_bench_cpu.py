@@ -25,19 +25,23 @@ def test_more_than_one_gpu_is_refused_with_a_message():
 
 
 def test_algorithmic_bytes_per_pass():
-    # 3D, 8 rows, FP64: x 2 arrays, y 3, last pass 3 + 2/3 (q^n in stages 2 and 3)
-    assert bench.pass_bytes_per_cell("pass_x", 8, 8, 3) == 128
+    # 3D, 8 rows, FP64, passes z, y, x: z 2 arrays, y 3, x (last) 3 + 2/3
+    # (q^n in stages 2 and 3)
+    assert bench.pass_bytes_per_cell("pass_z", 8, 8, 3) == 128
     assert bench.pass_bytes_per_cell("pass_y", 8, 8, 3) == 192
-    assert bench.pass_bytes_per_cell("pass_z", 8, 8, 3) == pytest.approx(234.6667, rel=1e-4)
+    assert bench.pass_bytes_per_cell("pass_x", 8, 8, 3) == pytest.approx(234.6667, rel=1e-4)
     assert bench.pass_bytes_per_cell("signal", 8, 8, 3) == 64
-    # 2D: the y pass is the last one
-    assert bench.pass_bytes_per_cell("pass_y", 7, 8, 2) == pytest.approx((3 + 2 / 3) * 56)
+    # 2D: y first, x last
+    assert bench.pass_bytes_per_cell("pass_y", 7, 8, 2) == 2 * 56
+    assert bench.pass_bytes_per_cell("pass_x", 7, 8, 2) == pytest.approx((3 + 2 / 3) * 56)
+    # 1D: the x pass alone reads q_k and q^n and writes the next state
+    assert bench.pass_bytes_per_cell("pass_x", 3, 8, 1) == pytest.approx((2 + 2 / 3) * 24)
 
 
 def test_roofline_fields_and_traffic_guard():
-    kinds = {"pass_x": (30.0, 60), "pass_y": (45.0, 60), "pass_z": (58.0, 60)}
+    kinds = {"pass_x": (58.0, 60), "pass_y": (45.0, 60), "pass_z": (30.0, 60)}
     r = bench.roofline_of(kinds, 8, 8, 3, 16777216, "fp64")
-    assert r["kernel"] == "pass_z" and r["bound"] == "hbm" and r["unit"] == "GB/s"
+    assert r["kernel"] == "pass_x" and r["bound"] == "hbm" and r["unit"] == "GB/s"
     assert r["frac"] == pytest.approx(r["achieved"] / r["peak"], rel=1e-3)
     # a different grid size never picks up the committed 256^3 counters
-    assert bench.measured_traffic_bytes("pass_z", "fp64", 100) is None
+    assert bench.measured_traffic_bytes("pass_x", "fp64", 100) is None
