@@ -85,7 +85,7 @@ struct mfc_ctx {
   void* q1;           // stage state 1
   void* q2;           // stage state 2
   double* scal;       // [0] smax, [1] dt
-  double* partial;    // reduction partials (kReduceBlocks * neq)
+  double* partial;    // reduction partials (see partial_len)
   int* flag;          // non-finite flag
   int device;
   std::string err;
@@ -262,6 +262,14 @@ int mfc_validate(const mfc_problem* p) {
   return MFC_OK;
 }
 
+// Partials buffer: the fixed-shape reductions (kReduceBlocks per row, up to
+// 8 rows) and the signal maxima of the first axis pass of a CFL step.
+static size_t partial_len(const mfc_problem& p) {
+  const long long red = (long long)mfc::kReduceBlocks * 8;
+  const long long sig = mfc::signal_partials(p.ndim, p.n);
+  return (size_t)(red > sig ? red : sig);
+}
+
 int mfc_create(const mfc_problem* p, mfc_ctx** out) {
   if (!out) return MFC_ERR_ARG;
   *out = nullptr;
@@ -287,7 +295,7 @@ int mfc_create(const mfc_problem* p, mfc_ctx** out) {
   bool ok = hipMalloc(&c->acc, bytes) == hipSuccess && hipMalloc(&c->q1, bytes) == hipSuccess &&
             hipMalloc(&c->q2, bytes) == hipSuccess &&
             hipMalloc((void**)&c->scal, 4 * sizeof(double)) == hipSuccess &&
-            hipMalloc((void**)&c->partial, (size_t)mfc::kReduceBlocks * 8 * sizeof(double)) == hipSuccess &&
+            hipMalloc((void**)&c->partial, partial_len(c->prob) * sizeof(double)) == hipSuccess &&
             hipMalloc((void**)&c->flag, sizeof(int)) == hipSuccess;
   if (ok) ok = hipMemset(c->flag, 0, sizeof(int)) == hipSuccess;
   if (ok) ok = hipMemset(c->scal, 0, 4 * sizeof(double)) == hipSuccess;
@@ -395,13 +403,21 @@ hipError_t step_t(mfc_ctx* c, Real* q, double cfl, double dt_fixed, double t_rem
                   hipStream_t s) {
   const int nf = c->prob.num_fluids, nd = c->prob.ndim;
   hipError_t e;
-  mfc::StageArgs st{1, dt_fixed, nullptr};
+  mfc::StageArgs st{1, dt_fixed, nullptr, nullptr};
+  // 2D / 3D: the first axis pass of stage 1 forms the signal maxima while it
+  // loads q^n, and dt is formed on the device before the x pass reads it
+  mfc::SignalFuse sig{c->partial, cfl, t_remaining, &c->scal[0], &c->scal[1], dt_user};
+  const mfc::SignalFuse* sigp = nullptr;
   if (cfl > 0.0) {
-    if (c->timer) c->timer->begin(mfc::KIND_SIGNAL, s);
-    e = mfc::launch_max_signal<Real>(nf, nd, c->pm, q, c->partial, &c->scal[0], cfl, t_remaining, &c->scal[1],
-                                     dt_user, c->flag, s);
-    if (c->timer) c->timer->end(mfc::KIND_SIGNAL, s);
-    if (e != hipSuccess) return e;
+    if (nd >= 2) {
+      sigp = &sig;
+    } else {
+      if (c->timer) c->timer->begin(mfc::KIND_SIGNAL, s);
+      e = mfc::launch_max_signal<Real>(nf, nd, c->pm, q, c->partial, &c->scal[0], cfl, t_remaining, &c->scal[1],
+                                       dt_user, c->flag, s);
+      if (c->timer) c->timer->end(mfc::KIND_SIGNAL, s);
+      if (e != hipSuccess) return e;
+    }
     st.dt_ptr = &c->scal[1];
   } else if (dt_user) {
     e = mfc::launch_set_scalar(dt_user, dt_fixed, s);
@@ -411,7 +427,7 @@ hipError_t step_t(mfc_ctx* c, Real* q, double cfl, double dt_fixed, double t_rem
   Real* q2 = (Real*)c->q2;
   Real* acc = (Real*)c->acc;
   st.stage = 1;
-  e = mfc::launch_rhs<Real>(nf, nd, c->pm, q, acc, q, q1, st, true, c->flag, s, c->timer);
+  e = mfc::launch_rhs<Real>(nf, nd, c->pm, q, acc, q, q1, st, true, c->flag, s, c->timer, sigp);
   if (e != hipSuccess) return e;
   st.stage = 2;
   e = mfc::launch_rhs<Real>(nf, nd, c->pm, q1, acc, q, q2, st, true, c->flag, s, c->timer);

@@ -413,6 +413,35 @@ __device__ __forceinline__ void weno5_m(float a, float b, float c, float d, floa
   fr = c + (er0 * r0 + er1 * r1 + er2 * r2) * __builtin_amdgcn_rcpf(6.0f * (er0 + er1 + er2));
 }
 
+// Maximum over the 64 lanes of a wave (NaN-ignoring, as fmax).
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+  return v;
+}
+
+// Signal speed of one cell for the CFL step: sum_d (|u_d| + c)/dx_d from the
+// conservative U and primitive W of the cell (c: frozen-mixture sound speed).
+// bad: c^2 <= 0 or a non-finite result.
+template <int NF, int D>
+__device__ __forceinline__ double cell_signal(const Params& pm, const double* U, const double* W, bool& bad) {
+  using R = Rows<NF, D>;
+  double rho = U[0];
+  if constexpr (NF == 2) rho = U[0] + U[1];
+  double Gam, Pi;
+  if constexpr (NF == 2)
+    mixture<NF, double>(pm, U[R::ALPHA], U[R::ALPHA + 1], Gam, Pi);
+  else
+    mixture<NF, double>(pm, 1.0, 0.0, Gam, Pi);
+  const double c2 = sound_speed_sq(rho, W[R::E], Gam, Pi);
+  const double cs = sqrt(c2);
+  double s = 0.0;
+#pragma unroll
+  for (int d = 0; d < D; ++d) s += (fabs(W[R::MOM + d]) + cs) * pm.inv_dx[d];
+  bad = !(c2 > 0.0) || !isfinite(s);
+  return s;
+}
+
 // The reconstruction of a kernel instantiation: WV = 0 WENO5-JS, 1 WENO5-Z,
 // 2 TENO5, 3 WENO5-M.  (A compile-time choice: a run-time branch inside the unrolled row
 // loops would make every kernel hold the registers of all of them.)

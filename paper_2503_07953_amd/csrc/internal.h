@@ -7,14 +7,30 @@
 
 namespace mfc {
 
-// Output mode of an axis pass.
-enum { MODE_WRITE = 0, MODE_ACC = 1, MODE_STEP = 2 };
+// Output mode of an axis pass.  MODE_SIGNAL (with MODE_WRITE, on the first
+// pass of a CFL step's first stage) also forms the block maxima of the signal
+// speed of every loaded cell.
+enum { MODE_WRITE = 0, MODE_ACC = 1, MODE_STEP = 2, MODE_SIGNAL = 4 };
 
 // Stage description for the fused SSP-RK3 combination.
 struct StageArgs {
   int stage;              // 1, 2 or 3
   double dt;              // used when dt_ptr is null
   const double* dt_ptr;   // device dt (CFL steps)
+  double* sig_partial;    // MODE_SIGNAL: one maximum per block of the pass
+};
+
+// CFL time step formed inside the first RHS evaluation of a step (2D and 3D):
+// the first axis pass writes per-block signal maxima to `partial`, then one
+// block forms smax, dt = cfl/smax (clipped to t_remaining when > 0) and
+// writes them to smax_out, dt_out and (if not null) dt_user.
+struct SignalFuse {
+  double* partial;
+  double cfl;
+  double t_remaining;
+  double* smax_out;
+  double* dt_out;
+  double* dt_user;
 };
 
 // Kinds of timed launches (see mfc_set_timing).
@@ -35,7 +51,14 @@ constexpr int kReduceThreads = 256;
 template <typename Real>
 hipError_t launch_rhs(int nf, int ndim, const Params& pm, const Real* qk, Real* acc, const Real* qn,
                       Real* qout, StageArgs st, bool final_step, int* flag, hipStream_t s,
-                      PassTimer* tm = nullptr);
+                      PassTimer* tm = nullptr, const SignalFuse* sig = nullptr);
+
+// Length of the partials buffer that SignalFuse needs for a grid (the block
+// count of the first axis pass; 0 in 1D, where the signal is a kernel of its own).
+long long signal_partials(int ndim, const int* n);
+
+hipError_t launch_finalize_dt(const double* partial, int nparts, double cfl, double t_remaining, double* smax_out,
+                              double* dt_out, double* dt_user, hipStream_t s);
 
 template <typename Real>
 hipError_t launch_max_signal(int nf, int ndim, const Params& pm, const Real* q, double* partial,

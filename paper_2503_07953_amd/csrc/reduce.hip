@@ -10,12 +10,6 @@
 
 namespace mfc {
 
-__device__ __forceinline__ double wave_max(double v) {
-#pragma unroll
-  for (int o = 32; o >= 1; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
-  return v;
-}
-
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
   for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
@@ -39,19 +33,9 @@ __global__ __launch_bounds__(kReduceThreads) void max_signal_partial(Params pm, 
 #pragma unroll
     for (int v = 0; v < NEQ; ++v) U[v] = double(q[v * nc + c]);
     cons_to_prim<NF, D>(pm, U, W);
-    double rho = U[0];
-    if constexpr (NF == 2) rho = U[0] + U[1];
-    double Gam, Pi;
-    if constexpr (NF == 2)
-      mixture<NF, double>(pm, U[R::ALPHA], U[R::ALPHA + 1], Gam, Pi);
-    else
-      mixture<NF, double>(pm, 1.0, 0.0, Gam, Pi);
-    const double c2 = sound_speed_sq(rho, W[R::E], Gam, Pi);
-    const double cs = sqrt(c2);
-    double s = 0.0;
-#pragma unroll
-    for (int d = 0; d < D; ++d) s += (fabs(W[R::MOM + d]) + cs) * pm.inv_dx[d];
-    bad |= !(c2 > 0.0) || !isfinite(s);
+    bool b;
+    const double s = cell_signal<NF, D>(pm, U, W, b);
+    bad |= b;
     smax = (s > smax) ? s : smax;  // NaN never wins; it is flagged instead
   }
   if (bad) atomicOr(flag, 1);
@@ -71,8 +55,17 @@ __global__ __launch_bounds__(kReduceThreads) void finalize_dt(const double* __re
                                                               double* __restrict__ smax_out,
                                                               double* __restrict__ dt_out,
                                                               double* __restrict__ dt_user) {
-  double m = 0.0;
-  for (int i = threadIdx.x; i < nparts; i += blockDim.x) m = fmax(m, partial[i]);
+  // eight independent running maxima per thread keep eight loads in flight
+  // (max is exact, so the order of the partials does not matter)
+  double mk[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  const int bd = blockDim.x;
+  int i = threadIdx.x;
+  for (; i + 7 * bd < nparts; i += 8 * bd) {
+#pragma unroll
+    for (int k = 0; k < 8; ++k) mk[k] = fmax(mk[k], partial[i + k * bd]);
+  }
+  for (; i < nparts; i += bd) mk[0] = fmax(mk[0], partial[i]);
+  double m = fmax(fmax(fmax(mk[0], mk[1]), fmax(mk[2], mk[3])), fmax(fmax(mk[4], mk[5]), fmax(mk[6], mk[7])));
   __shared__ double red[kReduceThreads / 64];
   m = wave_max(m);
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
@@ -88,6 +81,13 @@ __global__ __launch_bounds__(kReduceThreads) void finalize_dt(const double* __re
       if (dt_user) *dt_user = dt;
     }
   }
+}
+
+hipError_t launch_finalize_dt(const double* partial, int nparts, double cfl, double t_remaining, double* smax_out,
+                              double* dt_out, double* dt_user, hipStream_t s) {
+  hipLaunchKernelGGL(finalize_dt, dim3(1), dim3(kReduceThreads), 0, s, partial, nparts, cfl, t_remaining, smax_out,
+                     dt_out, dt_user);
+  return hipGetLastError();
 }
 
 template <typename Real>

@@ -108,6 +108,13 @@ __global__ __launch_bounds__((Tile<DIR, D, Real>::NT)) void sweep_kernel(Params 
   }
 
   // ---- (a) load + convert the tile and its halo into LDS -------------------
+  // MODE_SIGNAL: the signal speed of the tile's own cells (slots 3 .. 2 + OUT,
+  // inside the grid) as well; the tiles partition the grid, so the block
+  // maxima cover every cell once.
+  constexpr bool kSignal = (MODE & MODE_SIGNAL) != 0;
+  __shared__ double sred[kSignal ? TL::NT / 64 : 1];
+  double smax = 0.0;
+  bool sbad = false;
   for (int L = tid; L < TL::SA * TL::TB; L += TL::NT) {
     int s, bb;
     if constexpr (DIR == 0) {
@@ -141,8 +148,28 @@ __global__ __launch_bounds__((Tile<DIR, D, Real>::NT)) void sweep_kernel(Params 
     cons_to_prim<NF, D>(pm, U, W);
 #pragma unroll
     for (int v = 0; v < NEQ; ++v) sh[lds_index<DIR, D, Real>(v, s, bb)] = Real(W[v]);
+    if constexpr (kSignal) {
+      if (s >= 3 && s < 3 + TL::OUT && pos < nd) {
+        bool b;
+        const double sg = cell_signal<NF, D>(pm, U, W, b);
+        sbad |= b;
+        smax = (sg > smax) ? sg : smax;  // NaN never wins; it is flagged instead
+      }
+    }
+  }
+  if constexpr (kSignal) {
+    if (sbad) atomicOr(flag, 1);
+    smax = wave_max(smax);
+    if ((tid & 63) == 0) sred[tid >> 6] = smax;
   }
   __syncthreads();
+  if constexpr (kSignal) {
+    if (tid == 0) {
+      double m = sred[0];
+      for (int w = 1; w < TL::NT / 64; ++w) m = fmax(m, sred[w]);
+      st.sig_partial[blockIdx.x + (long long)gridDim.x * (blockIdx.y + (long long)gridDim.y * blockIdx.z)] = m;
+    }
+  }
 
   // this thread's reconstruction centre and line
   const int c = org - 1 + a;
@@ -283,19 +310,57 @@ static hipError_t launch_one(const Params& pm, const Real* qk, Real* acc, const 
   return hipGetLastError();
 }
 
-// All axes of one RHS evaluation.  final_step: the last axis combines into qout.
+// Blocks of the first axis pass of a 2D / 3D evaluation (y in 2D, z in 3D).
+template <int D, typename Real>
+static long long first_pass_blocks(const int* n) {
+  using TL = Tile<D - 1, D, Real>;
+  const long long bx = (n[0] + TL::TB - 1) / TL::TB;
+  if constexpr (D == 2)
+    return bx * ((n[1] + TL::OUT - 1) / TL::OUT) * n[2];
+  else
+    return bx * n[1] * ((n[2] + TL::OUT - 1) / TL::OUT);
+}
+
+long long signal_partials(int ndim, const int* n) {
+  if (ndim == 2) {
+    const long long a = first_pass_blocks<2, double>(n), b = first_pass_blocks<2, float>(n);
+    return a > b ? a : b;
+  }
+  if (ndim == 3) {
+    const long long a = first_pass_blocks<3, double>(n), b = first_pass_blocks<3, float>(n);
+    return a > b ? a : b;
+  }
+  return 0;
+}
+
+// All axes of one RHS evaluation, z (or y) first and x last.  final_step: the
+// x pass combines into qout.  sig (2D / 3D): the first pass also forms the
+// signal-speed block maxima and dt is formed before the x pass reads it.
 template <int NF, int D, typename Real, int WV>
 static hipError_t launch_rhs_t(const Params& pm, const Real* qk, Real* acc, const Real* qn, Real* qout,
-                               StageArgs st, bool final_step, int* flag, hipStream_t s, PassTimer* tm) {
+                               StageArgs st, bool final_step, int* flag, hipStream_t s, PassTimer* tm,
+                               const SignalFuse* sig) {
   hipError_t e = hipSuccess;
   if constexpr (D == 1) {
+    if (sig) return hipErrorInvalidValue;
     if (final_step)
       e = launch_one<NF, D, 0, Real, MODE_STEP, WV>(pm, qk, acc, qn, qout, st, flag, s, tm);
     else
       e = launch_one<NF, D, 0, Real, MODE_WRITE, WV>(pm, qk, acc, qn, qout, st, flag, s, tm);
   } else {
     constexpr int FIRST = D - 1;
-    e = launch_one<NF, D, FIRST, Real, MODE_WRITE, WV>(pm, qk, acc, qn, qout, st, flag, s, tm);
+    if (sig) {
+      StageArgs s1 = st;
+      s1.sig_partial = sig->partial;
+      e = launch_one<NF, D, FIRST, Real, MODE_WRITE | MODE_SIGNAL, WV>(pm, qk, acc, qn, qout, s1, flag, s, tm);
+      if (e != hipSuccess) return e;
+      if (tm) tm->begin(KIND_SIGNAL, s);
+      e = launch_finalize_dt(sig->partial, (int)first_pass_blocks<D, Real>(pm.n), sig->cfl, sig->t_remaining,
+                             sig->smax_out, sig->dt_out, sig->dt_user, s);
+      if (tm) tm->end(KIND_SIGNAL, s);
+    } else {
+      e = launch_one<NF, D, FIRST, Real, MODE_WRITE, WV>(pm, qk, acc, qn, qout, st, flag, s, tm);
+    }
     if (e != hipSuccess) return e;
     if constexpr (D == 3) {
       e = launch_one<NF, D, 1, Real, MODE_ACC, WV>(pm, qk, acc, qn, qout, st, flag, s, tm);
@@ -311,13 +376,15 @@ static hipError_t launch_rhs_t(const Params& pm, const Real* qk, Real* acc, cons
 
 template <typename Real>
 hipError_t launch_rhs(int nf, int ndim, const Params& pm, const Real* qk, Real* acc, const Real* qn,
-                      Real* qout, StageArgs st, bool final_step, int* flag, hipStream_t s, PassTimer* tm) {
-#define MFC_CASE(NF, D)                                                                        \
-  if (nf == NF && ndim == D)                                                                   \
-    return pm.weno_variant == 1   ? launch_rhs_t<NF, D, Real, 1>(pm, qk, acc, qn, qout, st, final_step, flag, s, tm) \
-           : pm.weno_variant == 2 ? launch_rhs_t<NF, D, Real, 2>(pm, qk, acc, qn, qout, st, final_step, flag, s, tm) \
-           : pm.weno_variant == 3 ? launch_rhs_t<NF, D, Real, 3>(pm, qk, acc, qn, qout, st, final_step, flag, s, tm) \
-                                  : launch_rhs_t<NF, D, Real, 0>(pm, qk, acc, qn, qout, st, final_step, flag, s, tm);
+                      Real* qout, StageArgs st, bool final_step, int* flag, hipStream_t s, PassTimer* tm,
+                      const SignalFuse* sig) {
+#define MFC_ARGS pm, qk, acc, qn, qout, st, final_step, flag, s, tm, sig
+#define MFC_CASE(NF, D)                                                        \
+  if (nf == NF && ndim == D)                                                   \
+    return pm.weno_variant == 1   ? launch_rhs_t<NF, D, Real, 1>(MFC_ARGS)     \
+           : pm.weno_variant == 2 ? launch_rhs_t<NF, D, Real, 2>(MFC_ARGS)     \
+           : pm.weno_variant == 3 ? launch_rhs_t<NF, D, Real, 3>(MFC_ARGS)     \
+                                  : launch_rhs_t<NF, D, Real, 0>(MFC_ARGS);
   MFC_CASE(1, 1)
   MFC_CASE(1, 2)
   MFC_CASE(1, 3)
@@ -325,12 +392,14 @@ hipError_t launch_rhs(int nf, int ndim, const Params& pm, const Real* qk, Real* 
   MFC_CASE(2, 2)
   MFC_CASE(2, 3)
 #undef MFC_CASE
+#undef MFC_ARGS
   return hipErrorInvalidValue;
 }
 
 template hipError_t launch_rhs<double>(int, int, const Params&, const double*, double*, const double*,
-                                       double*, StageArgs, bool, int*, hipStream_t, PassTimer*);
+                                       double*, StageArgs, bool, int*, hipStream_t, PassTimer*,
+                                       const SignalFuse*);
 template hipError_t launch_rhs<float>(int, int, const Params&, const float*, float*, const float*, float*,
-                                      StageArgs, bool, int*, hipStream_t, PassTimer*);
+                                      StageArgs, bool, int*, hipStream_t, PassTimer*, const SignalFuse*);
 
 }  // namespace mfc
