@@ -27,6 +27,22 @@
 
 namespace mfc {
 
+// Accumulator access with or without the non-temporal cache hint.
+template <bool NT, typename Real>
+__device__ __forceinline__ Real ld_acc(const Real* p) {
+  if constexpr (NT)
+    return __builtin_nontemporal_load(p);
+  else
+    return *p;
+}
+template <bool NT, typename Real>
+__device__ __forceinline__ void st_acc(Real v, Real* p) {
+  if constexpr (NT)
+    __builtin_nontemporal_store(v, p);
+  else
+    *p = v;
+}
+
 template <int DIR, int D, typename Real>
 struct Tile {
   // TA: reconstruction centres per tile along the sweep axis (outputs TA - 2)
@@ -190,12 +206,15 @@ __global__ __launch_bounds__((Tile<DIR, D, Real>::NT)) void sweep_kernel(Params 
   // the pass got 12 % slower)
   constexpr bool kPrefetch =
       (DIR == 1 && MODE == MODE_ACC) || (DIR == 0 && D > 1 && (MODE & MODE_ACC) && sizeof(Real) == 4);
+  // the y and z passes stream the accumulator with the non-temporal hint (the
+  // y pass gained 4 % in FP64; in the x pass it cost 1.5-3 %)
+  constexpr bool kNT = DIR != 0;
   Real pre[kPrefetch ? NEQ : 1];
   if constexpr (kPrefetch) {
     if (line_ok && a >= 1 && a <= TL::TA - 2 && c >= 0 && c < nd) {
       const long long cell = (DIR == 1) ? ((long long)oz * ny + c) * nx + ox : ((long long)oz * ny + oy) * nx + c;
 #pragma unroll
-      for (int v = 0; v < NEQ; ++v) pre[v] = acc[v * nc + cell];
+      for (int v = 0; v < NEQ; ++v) pre[v] = ld_acc<kNT>(&acc[v * nc + cell]);
     }
   }
 
@@ -265,7 +284,7 @@ __global__ __launch_bounds__((Tile<DIR, D, Real>::NT)) void sweep_kernel(Params 
     if constexpr (kPrefetch)
       r = pre[v] + Dv;
     else if constexpr (MODE & MODE_ACC)
-      r = acc[e] + Dv;
+      r = ld_acc<kNT>(&acc[e]) + Dv;
     if constexpr (MODE & MODE_STEP) {
       // SSP-RK3, Shu-Osher form (Sec. 3.4), combined in double
       const double dt = st.dt_ptr ? *st.dt_ptr : st.dt;
@@ -279,7 +298,7 @@ __global__ __launch_bounds__((Tile<DIR, D, Real>::NT)) void sweep_kernel(Params 
         out = (1.0 / 3.0) * double(qn[e]) + (2.0 / 3.0) * qs;
       qout[e] = Real(out);
     } else {
-      acc[e] = r;
+      st_acc<kNT>(r, &acc[e]);
     }
   }
 }
