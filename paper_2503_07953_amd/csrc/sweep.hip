@@ -19,7 +19,8 @@
 //
 // Tile shapes (wave64): along x the centres of a tile are the 64 lanes of a
 // wave, one wave per x-row, 4 rows per block; along y and z, 32 x-lanes by 16
-// centres along the sweep axis (512 threads).  Every access to q is to x-
+// centres along the sweep axis (512 threads; in FP64, 16 lanes by 16 centres
+// for y in 3D and 16 lanes by 32 centres for z).  Every access to q is to x-
 // contiguous runs, so all three passes read HBM coalesced without any
 // transposition of the state.
 #include "device.h"
@@ -46,11 +47,13 @@ __device__ __forceinline__ void st_acc(Real v, Real* p) {
 template <int DIR, int D, typename Real>
 struct Tile {
   // TA: reconstruction centres per tile along the sweep axis (outputs TA - 2)
-  // TB: independent lines across the sweep axis (x lanes for y and z).  The
-  // FP64 middle (y) pass of a 3D stage runs 16 lanes (256-thread blocks, twice
-  // the blocks per CU); measured faster there, slower for z and for FP32.
-  static constexpr int TA = (DIR == 0) ? 64 : 16;
-  static constexpr int TB = (DIR == 0) ? ((D == 1) ? 1 : 4) : ((DIR == 1 && D == 3 && sizeof(Real) == 8) ? 16 : 32);
+  // TB: independent lines across the sweep axis (x lanes for y and z).  In
+  // FP64 the y pass of a 3D stage runs 16 lanes (256-thread blocks, twice the
+  // blocks per CU) and the z pass 32 centres x 16 lanes (halo loads 36 per 30
+  // outputs instead of 20 per 14); both measured faster in FP64, slower in FP32.
+  static constexpr bool kF64 = sizeof(Real) == 8;
+  static constexpr int TA = (DIR == 0) ? 64 : ((DIR == 2 && kF64) ? 32 : 16);
+  static constexpr int TB = (DIR == 0) ? ((D == 1) ? 1 : 4) : ((kF64 && (DIR == 2 || D == 3)) ? 16 : 32);
   static constexpr int NT = TA * TB;
   static constexpr int OUT = TA - 2;
   static constexpr int SA = TA + 4;  // LDS slots along the sweep axis
