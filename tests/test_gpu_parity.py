@@ -394,3 +394,67 @@ def test_periodic_slab_512_full_size_rhs_step_and_conservation():
     drift = np.abs(sums1 - sums0)[:6] / scale[:6]
     _say("C4 conservation drift", drift)
     assert np.all(drift <= 1e-13), drift
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("nd", [2, 3])
+def test_fused_cfl_dt_equals_the_standalone_signal(nd, precision):
+    """In 2D and 3D the first axis pass of a CFL step forms the signal maxima;
+    dt must be exactly cfl / mfc_max_signal (both divisions in double), the
+    t_remaining clip must apply, and a fixed-dt step with that value must give
+    the same state bit for bit."""
+    from paper_2503_07953_amd.solver import Solver
+    n = (40, 36, 30)[:nd]
+    bc = (W.PERIODIC, W.SLIPWALL, W.EXTRAP)[:nd]
+    c = W.random_case(nd, n, nf=2, seed=81, bc=bc, speed=150.0)
+    S = Solver.from_case(c, precision=precision)
+    q = S.prim_to_cons(S.to_device(c.w))
+    smax = S.max_signal(q).item()
+    dt = torch.zeros(1, dtype=torch.float64, device="cuda")
+    q_cfl = q.clone()
+    S.step(q_cfl, cfl=0.4, dt_out=dt)
+    assert dt.item() == 0.4 / smax
+    q_clip = q.clone()
+    S.step(q_clip, cfl=0.4, t_remaining=0.25 * (0.4 / smax), dt_out=dt)
+    assert dt.item() == 0.25 * (0.4 / smax)
+    q_fix = q.clone()
+    S.step(q_fix, dt_fixed=0.4 / smax)
+    S.check()
+    assert torch.equal(q_cfl, q_fix)
+
+
+@pytest.mark.slow
+def test_chunked_x_launch_and_indices_past_2_31():
+    """3 x 65535 x 1400 cells, 8 rows, FP32: 2.2e9 elements, so element
+    indices pass 2^31, and 2.3e7 x-pass blocks, so that pass runs as two
+    launches (chunks of 2^24 blocks).  The state repeats a 3 x 65535 x 14 block
+    100 times along a periodic z: every cell sees the stencil values of its
+    twin in the small periodic grid, so the RHS and one CFL step must tile the
+    small grid's results bit for bit (dt included)."""
+    from paper_2503_07953_amd.solver import Solver
+    P, reps = 14, 100
+    c = W.random_case(3, (3, 65535, P), nf=2, seed=71, bc=(W.PERIODIC, W.EXTRAP, W.PERIODIC), speed=100.0)
+    small = Solver.from_case(c, precision="fp32")
+    q_small = small.prim_to_cons(small.to_device(c.w))
+    kw = dict(c.problem_kwargs())
+    kw["n"] = (3, 65535, P * reps)
+    _say("large grid", kw["n"])
+    big = Solver(**kw, precision="fp32")
+    q_big = q_small.repeat(1, reps, 1, 1)
+    neq, ny, nx = q_small.shape[0], 65535, 3
+
+    def tiled(a_big, a_small):
+        return torch.equal(a_big.view(neq, reps, P, ny, nx), a_small.unsqueeze(1).expand(neq, reps, P, ny, nx))
+
+    r_small = small.rhs(q_small)
+    r_big = big.rhs(q_big)
+    assert tiled(r_big, r_small)
+    del r_big
+    dts = torch.zeros(1, dtype=torch.float64, device="cuda")
+    dtb = torch.zeros(1, dtype=torch.float64, device="cuda")
+    small.step(q_small, cfl=0.5, dt_out=dts)
+    big.step(q_big, cfl=0.5, dt_out=dtb)
+    small.check()
+    big.check()
+    assert dts.item() == dtb.item()
+    assert tiled(q_big, q_small)
