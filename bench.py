@@ -53,7 +53,7 @@ def pass_bytes_per_cell(kind, neq, esize, ndim, stage_mix=(1, 1, 1)):
 
 
 # Algorithmic FP64 operations per cell for one axis pass of the 3D two-fluid
-# system (counted from the method's formulas; see DESIGN.md): cons->prim 21,
+# system (counted from the method's formulas): cons->prim 21,
 # WENO5-JS 97 per row x 8 rows, HLLC 106 per face, flux difference and
 # volume-fraction source 30.  The stage update adds 32 per cell on the last pass.
 FLOPS_PASS_3D2F = 21 + 97 * 8 + 106 + 30

@@ -55,7 +55,7 @@ def noise_floor(fn, q, trials=3, seed=5):
 
     Two correct float64 evaluations of an ill-conditioned map (here: WENO-JS
     derivatives, whose weights react strongly to rounding-level data) cannot
-    agree better than this spread; adjoint parity is judged against it.
+    agree better than this spread; adjoint parity is measured against it.
     """
     base = fn(q)
     rng = np.random.default_rng(seed)
