@@ -51,6 +51,7 @@ class OrcProblem(ctypes.Structure):
         ("pi_inf", ctypes.c_double * 2),
         ("weno_eps", ctypes.c_double),
         ("weno_variant", ctypes.c_int32),
+        ("riemann", ctypes.c_int32),
     ]
 
 
@@ -79,6 +80,7 @@ def lib():
             "orc_teno5_left": (ctypes.c_double, [dp, ctypes.c_double, ctypes.c_double]),
             "orc_teno5_right": (ctypes.c_double, [dp, ctypes.c_double, ctypes.c_double]),
             "orc_hllc": (ctypes.c_int, [P, ctypes.c_int, dp, dp, dp, dp]),
+            "orc_hll": (ctypes.c_int, [P, ctypes.c_int, dp, dp, dp, dp]),
             "orc_rhs": (ctypes.c_int, [P, dp, dp]),
             "orc_rhs_cells": (ctypes.c_int, [P, dp, ctypes.c_int64, i64p, dp]),
             "orc_max_signal": (ctypes.c_int, [P, dp, dp]),
@@ -99,7 +101,8 @@ def lib():
     return _lib
 
 
-def problem(ndim, n, num_fluids, dx, gamma, pi_inf, bc_lo, bc_hi, weno_eps=1e-6, weno_variant=0) -> OrcProblem:
+def problem(ndim, n, num_fluids, dx, gamma, pi_inf, bc_lo, bc_hi, weno_eps=1e-6, weno_variant=0,
+            riemann=0) -> OrcProblem:
     P = OrcProblem()
     P.ndim = ndim
     n = tuple(n) + (1,) * (3 - len(n))
@@ -114,6 +117,7 @@ def problem(ndim, n, num_fluids, dx, gamma, pi_inf, bc_lo, bc_hi, weno_eps=1e-6,
         P.pi_inf[i] = float(pi_inf[i]) if i < len(pi_inf) else float(pi_inf[0])
     P.weno_eps = weno_eps
     P.weno_variant = int(weno_variant)
+    P.riemann = int(riemann)
     return P
 
 
@@ -228,6 +232,15 @@ class Oracle:
         F = np.empty(self.neq)
         uf = ctypes.c_double()
         rc = self.L.orc_hllc(ctypes.byref(self.P), d, _dp(wl), _dp(wr), _dp(F), ctypes.byref(uf))
+        return F, uf.value, rc
+
+    def hll(self, d, wl, wr):
+        """HLL face flux and face velocity (Sec. 3.2.2)."""
+        wl = np.ascontiguousarray(wl, dtype=np.float64)
+        wr = np.ascontiguousarray(wr, dtype=np.float64)
+        F = np.empty(self.neq)
+        uf = ctypes.c_double()
+        rc = self.L.orc_hll(ctypes.byref(self.P), d, _dp(wl), _dp(wr), _dp(F), ctypes.byref(uf))
         return F, uf.value, rc
 
 

@@ -49,6 +49,7 @@ typedef struct {
   double gamma[2], pi_inf[2];
   double weno_eps;
   int32_t weno_variant; /* 0: WENO5-JS (Sec. 3.2.1), 1: WENO5-Z, 2: TENO5 (Sec. 4.2.2), 3: WENO5-M (Sec. 3.2.1) */
+  int32_t riemann;      /* 0: HLLC, 1: HLL (Sec. 3.2.2) */
 } orc_problem;
 
 /* ------------------------------------------------------------------------ */
@@ -84,6 +85,7 @@ int orc_validate(const orc_problem* P) {
     if (!(P->gamma[i] > 1.0) || !(P->pi_inf[i] >= 0.0)) return ORC_ERR_ARG;
   if (!(P->weno_eps > 0)) return ORC_ERR_ARG;
   if (P->weno_variant < 0 || P->weno_variant > 3) return ORC_ERR_ARG;
+  if (P->riemann < 0 || P->riemann > 1) return ORC_ERR_ARG;
   return ORC_OK;
 }
 
@@ -429,6 +431,53 @@ int orc_hllc(const orc_problem* P, int d, const double* WL, const double* WR, do
 }
 
 /* ------------------------------------------------------------------------ */
+/* HLL face solver (Sec. 3.2.2, from Toro's book): two waves S_L, S_R, the  */
+/* same estimates as HLLC, and one averaged state between them (no contact):*/
+/*   F = F_L if S_L >= 0, F_R if S_R <= 0, else                              */
+/*   F = (S_R F_L - S_L F_R + S_L S_R (U_R - U_L)) / (S_R - S_L).             */
+/* Readings (the paper prints no formula): the volume fractions take the    */
+/* same formula on their advective flux alpha u_n, and the face velocity of */
+/* the alpha source is the matching average u_f = (S_R u_L - S_L u_R) /     */
+/* (S_R - S_L) (u_L or u_R in the one-sided cases), so that a uniform alpha */
+/* stays uniform.                                                           */
+/* ------------------------------------------------------------------------ */
+int orc_hll(const orc_problem* P, int d, const double* WL, const double* WR, double* F, double* uf) {
+  int nf = P->num_fluids, neq = orc_num_eqs(P);
+  int ncons = row_E(P) + 1;
+  face_state L, R;
+  int bad = face_side(P, d, WL, &L);
+  bad |= face_side(P, d, WR, &R);
+  double sl_a = L.un - L.c, sl_b = R.un - R.c;
+  double sr_a = L.un + L.c, sr_b = R.un + R.c;
+  double SL = (sl_a <= sl_b) ? sl_a : sl_b;
+  double SR = (sr_a >= sr_b) ? sr_a : sr_b;
+  if (SL >= 0.0) {
+    for (int v = 0; v < ncons; ++v) F[v] = L.F[v];
+    *uf = L.un;
+    if (nf == 2)
+      for (int i = 0; i < 2; ++i) F[row_alpha(P, i)] = WL[row_alpha(P, i)] * L.un;
+  } else if (SR <= 0.0) {
+    for (int v = 0; v < ncons; ++v) F[v] = R.F[v];
+    *uf = R.un;
+    if (nf == 2)
+      for (int i = 0; i < 2; ++i) F[row_alpha(P, i)] = WR[row_alpha(P, i)] * R.un;
+  } else {
+    double den = SR - SL;
+    for (int v = 0; v < ncons; ++v) F[v] = (SR * L.F[v] - SL * R.F[v] + SL * SR * (R.U[v] - L.U[v])) / den;
+    *uf = (SR * L.un - SL * R.un) / den;
+    if (nf == 2)
+      for (int i = 0; i < 2; ++i) {
+        double aL = WL[row_alpha(P, i)], aR = WR[row_alpha(P, i)];
+        F[row_alpha(P, i)] = (SR * aL * L.un - SL * aR * R.un + SL * SR * (aR - aL)) / den;
+      }
+  }
+  for (int v = 0; v < neq; ++v)
+    if (!isfinite(F[v])) bad = 1;
+  if (!isfinite(*uf)) bad = 1;
+  return bad;
+}
+
+/* ------------------------------------------------------------------------ */
 /* Face flux along axis d at the face on the low side of cell idx (face     */
 /* m - 1/2 with m = idx[d]): cells m-3..m+2 are loaded (ghost layers mapped),*/
 /* converted to primitive variables, reconstructed component-wise (left     */
@@ -466,7 +515,7 @@ static int face_flux(const orc_problem* P, const double* q, int d, const int idx
       WR[v] = orc_weno5_js_right(fr, P->weno_eps);
     }
   }
-  return orc_hllc(P, d, WL, WR, F, uf);
+  return P->riemann == 1 ? orc_hll(P, d, WL, WR, F, uf) : orc_hllc(P, d, WL, WR, F, uf);
 }
 
 /* Contribution of axis d to the RHS of one cell (eq. eqn:rhs with s = 0 and

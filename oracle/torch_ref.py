@@ -41,7 +41,8 @@ def sqrt(x):
 
 
 class Problem:
-    def __init__(self, ndim, n, num_fluids, dx, gamma, pi_inf, bc_lo, bc_hi, weno_eps=1e-6, weno_variant=0):
+    def __init__(self, ndim, n, num_fluids, dx, gamma, pi_inf, bc_lo, bc_hi, weno_eps=1e-6, weno_variant=0,
+                 riemann=0):
         self.ndim = ndim
         self.n = tuple(n) + (1,) * (3 - len(n))
         self.nf = num_fluids
@@ -52,6 +53,7 @@ class Problem:
         self.bc_hi = tuple(bc_hi) + (EXTRAP,) * (3 - len(bc_hi))
         self.eps = weno_eps
         self.weno_variant = int(weno_variant)
+        self.riemann = int(riemann)
         self.neq = self.nf + ndim + 1 + (2 if self.nf == 2 else 0)
         self.G = [1.0 / (g - 1.0) for g in self.gamma]
         self.P = [g * p / (g - 1.0) for g, p in zip(self.gamma, self.pi_inf)]
@@ -237,35 +239,37 @@ def _max_first(a, b):
     return torch.where(a >= b, a, b)
 
 
+def _face_side(P: Problem, d, W):
+    """Face-side quantities of a reconstructed state: rho, u_n, p, E, c, U, F."""
+    nf, D = P.nf, P.ndim
+    rho = 0.0 + W[0] if nf == 1 else W[0] + W[1]
+    usq = 0.0
+    for e in range(D):
+        usq = usq + W[P.row_mom(e)] * W[P.row_mom(e)]
+    alpha = [W[P.row_alpha(i)] for i in range(2)] if nf == 2 else None
+    Gam, Pi = mixture(P, alpha)
+    p = W[P.row_E]
+    un = W[P.row_mom(d)]
+    E = Gam * p + Pi + 0.5 * rho * usq
+    c2 = ((Gam + 1.0) * p + Pi) / (Gam * rho)
+    c = sqrt(c2)
+    U, F = [], []
+    for i in range(nf):
+        U.append(W[i])
+        F.append(W[i] * un)
+    for e in range(D):
+        m = rho * W[P.row_mom(e)]
+        U.append(m)
+        F.append(m * un + p if e == d else m * un + 0.0)
+    U.append(E)
+    F.append((E + p) * un)
+    return dict(rho=rho, un=un, p=p, E=E, c=c, c2=c2, U=U, F=F)
+
+
 def hllc(P: Problem, d, WL, WR):
     """HLLC flux of every row and the face velocity, arrays over faces."""
     nf, D = P.nf, P.ndim
-
-    def side(W):
-        rho = 0.0 + W[0] if nf == 1 else W[0] + W[1]
-        usq = 0.0
-        for e in range(D):
-            usq = usq + W[P.row_mom(e)] * W[P.row_mom(e)]
-        alpha = [W[P.row_alpha(i)] for i in range(2)] if nf == 2 else None
-        Gam, Pi = mixture(P, alpha)
-        p = W[P.row_E]
-        un = W[P.row_mom(d)]
-        E = Gam * p + Pi + 0.5 * rho * usq
-        c2 = ((Gam + 1.0) * p + Pi) / (Gam * rho)
-        c = sqrt(c2)
-        U, F = [], []
-        for i in range(nf):
-            U.append(W[i])
-            F.append(W[i] * un)
-        for e in range(D):
-            m = rho * W[P.row_mom(e)]
-            U.append(m)
-            F.append(m * un + p if e == d else m * un + 0.0)
-        U.append(E)
-        F.append((E + p) * un)
-        return dict(rho=rho, un=un, p=p, E=E, c=c, c2=c2, U=U, F=F)
-
-    L, R = side(WL), side(WR)
+    L, R = _face_side(P, d, WL), _face_side(P, d, WR)
     SL = _min_first(L["un"] - L["c"], R["un"] - R["c"])
     SR = _max_first(L["un"] + L["c"], R["un"] + R["c"])
     Sstar = (R["p"] - L["p"] + L["rho"] * L["un"] * (SL - L["un"]) - R["rho"] * R["un"] * (SR - R["un"])) / (
@@ -296,6 +300,32 @@ def hllc(P: Problem, d, WL, WR):
     return torch.stack(F), uf, (L["c2"], R["c2"])
 
 
+def hll(P: Problem, d, WL, WR):
+    """HLL flux (Sec. 3.2.2): two waves, one averaged state; the volume
+    fractions take the same formula on alpha u_n and the face velocity is the
+    matching average (S_R u_L - S_L u_R)/(S_R - S_L)."""
+    nf, D = P.nf, P.ndim
+    L, R = _face_side(P, d, WL), _face_side(P, d, WR)
+    SL = _min_first(L["un"] - L["c"], R["un"] - R["c"])
+    SR = _max_first(L["un"] + L["c"], R["un"] + R["c"])
+    den = SR - SL
+    c1 = SL >= 0.0
+    c4 = SR <= 0.0
+    F = []
+    for v in range(nf + D + 1):
+        Fm = (SR * L["F"][v] - SL * R["F"][v] + SL * SR * (R["U"][v] - L["U"][v])) / den
+        F.append(torch.where(c1, L["F"][v], torch.where(c4, R["F"][v], Fm)))
+    um = (SR * L["un"] - SL * R["un"]) / den
+    uf = torch.where(c1, L["un"], torch.where(c4, R["un"], um))
+    if nf == 2:
+        for i in range(2):
+            a = P.row_alpha(i)
+            aL, aR = WL[a], WR[a]
+            Fm = (SR * aL * L["un"] - SL * aR * R["un"] + SL * SR * (aR - aL)) / den
+            F.append(torch.where(c1, aL * L["un"], torch.where(c4, aR * R["un"], Fm)))
+    return torch.stack(F), uf, (L["c2"], R["c2"])
+
+
 def axis_contribution(P: Problem, q, d):
     """D_d of eq. eqn:rhs for every cell (see oracle.c)."""
     n = P.n[d]
@@ -308,7 +338,7 @@ def axis_contribution(P: Problem, q, d):
     weno = {0: weno5_js_left, 1: weno5_z_left, 2: teno5_left, 3: weno5_m_left}[P.weno_variant]
     WL = weno(fl[0], fl[1], fl[2], fl[3], fl[4], P.eps)
     WR = weno(fr[4], fr[3], fr[2], fr[1], fr[0], P.eps)
-    F, uf, _ = hllc(P, d, WL, WR)
+    F, uf, _ = (hll if P.riemann == 1 else hllc)(P, d, WL, WR)
     inv_dx = 1.0 / P.dx[d]
     Flo, Fhi = _sl(F, ax, 0, n), _sl(F, ax, 1, n)
     Dv = inv_dx * (Flo - Fhi)

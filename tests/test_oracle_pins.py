@@ -603,11 +603,13 @@ def test_independent_torch_implementation_agrees_bitwise(nd, n, nf, bc):
     """The whole-array torch version (independent code) reproduces the oracle bit for bit."""
     for variant in (0, 1, 2, 3):
         _torch_agrees(nd, n, nf, bc, variant)
+    _torch_agrees(nd, n, nf, bc, 0, riemann=1)
 
 
-def _torch_agrees(nd, n, nf, bc, variant):
+def _torch_agrees(nd, n, nf, bc, variant, riemann=0):
     c = W.random_case(nd, n, nf=nf, seed=3, bc=bc)
     c.weno_variant = variant
+    c.riemann = riemann
     O = oracle.Oracle(c)
     q = O.prim_to_cons(c.w)
     P = TR.Problem.from_case(c)
@@ -633,6 +635,113 @@ def test_nonfinite_state_is_flagged():
 # --------------------------------------------------------------------------
 # C-6 equilibrium, C-7 / C-8 time stepping
 # --------------------------------------------------------------------------
+# --------------------------------------------------------------------------
+# HLL (Sec. 3.2.2): two waves, one averaged state between them
+# --------------------------------------------------------------------------
+def _oracle_hll(D, nf=2):
+    O = _oracle_for(D, nf)
+    O.P.riemann = 1
+    return O
+
+
+@pytest.mark.parametrize("nf,D", [(2, 3), (2, 2), (1, 3), (1, 1)])
+def test_hll_consistency(nf, D):
+    """F(w, w) equals the physical flux and u_f the normal velocity, whatever
+    the branch (subsonic states and |u| > c both drawn)."""
+    O = _oracle_hll(D, nf)
+    rng = np.random.default_rng(41)
+    for k in range(60):
+        w = _prim_state(rng, nf, D, speed=100.0 if k % 2 else 3000.0)
+        d = int(rng.integers(0, D))
+        F, uf, rc = O.hll(d, w, w)
+        assert rc == 0
+        Fp = _physical_flux(O, d, w, nf, D)
+        scale = np.abs(Fp) + abs(w[nf + D]) + 1e-300
+        assert np.all(np.abs(F - Fp) <= 1e-12 * scale)
+        assert abs(uf - w[nf + d]) <= 1e-12 * (abs(w[nf + d]) + 1)
+
+
+def test_hll_supersonic_upwind_exact():
+    O = _oracle_hll(1, 1)
+    wl = np.array([1.0, 3.0, 1.0])
+    wr = np.array([0.5, 2.5, 0.8])
+    F, uf, rc = O.hll(0, wl, wr)
+    assert np.array_equal(F, _physical_flux(O, 0, wl, 1, 1)) and uf == 3.0
+    wl2, wr2 = np.array([0.5, -2.5, 0.8]), np.array([1.0, -3.0, 1.0])
+    F, uf, rc = O.hll(0, wl2, wr2)
+    assert np.array_equal(F, _physical_flux(O, 0, wr2, 1, 1)) and uf == -3.0
+
+
+def test_hll_mirror_symmetry():
+    """Reflecting the face (swap the sides, negate the normal velocity) negates
+    every flux except the normal momentum one, and negates u_f: a swapped
+    S_L / S_R or F_L / F_R breaks this."""
+    O = _oracle_hll(3, 2)
+    rng = np.random.default_rng(42)
+    for _ in range(40):
+        wl, wr = _prim_state(rng, 2, 3), _prim_state(rng, 2, 3)
+        d = int(rng.integers(0, 3))
+        F1, u1, _ = O.hll(d, wl, wr)
+        ml, mr = wr.copy(), wl.copy()
+        ml[2 + d] *= -1.0
+        mr[2 + d] *= -1.0
+        F2, u2, _ = O.hll(d, ml, mr)
+        sign = -np.ones_like(F1)
+        sign[2 + d] = 1.0
+        scale = np.abs(F1).max()
+        assert np.all(np.abs(F2 - sign * F1) <= 1e-12 * scale + 1e-12 * np.abs(F1))
+        assert abs(u2 + u1) <= 1e-12 * (abs(u1) + 1)
+
+
+def test_hll_smears_a_resting_contact_that_hllc_keeps():
+    """At a resting contact (same p, u = 0, different densities) both solvers
+    give the momentum flux p exactly, but HLL moves mass across it (its single
+    averaged state has no contact), while HLLC's mass flux is zero."""
+    O = _oracle_for(3, 2)
+    Oh = _oracle_hll(3, 2)
+    wl = np.array([0.7 * 1000.0, 0.3 * 1.0, 0.0, 0.0, 0.0, 1e5, 0.7, 0.3])
+    wr = np.array([0.2 * 1000.0, 0.8 * 1.0, 0.0, 0.0, 0.0, 1e5, 0.2, 0.8])
+    F, uf, _ = O.hllc(0, wl, wr)
+    Fh, ufh, _ = Oh.hll(0, wl, wr)
+    assert F[0] == 0.0 and uf == 0.0
+    assert Fh[0] != 0.0 and np.sign(Fh[0]) == np.sign(wl[0] - wr[0])
+    assert F[2] == 1e5 and abs(Fh[2] - 1e5) <= 1e-12 * 1e5
+
+
+def test_hll_keeps_pressure_and_velocity_across_an_advected_interface():
+    """The alpha rows take the HLL formula on alpha u_n, the same operator as
+    the partial densities, and u_f the matching average: an advected
+    interface then keeps p and u uniform (any other alpha transport would
+    make the pressure oscillate)."""
+    c = _case_1d_two_fluid(100)
+    c.riemann = 1
+    O = oracle.Oracle(c)
+    q = O.prim_to_cons(c.w)
+    O.run(q, 400, cfl=0.5)
+    w = O.cons_to_prim(q)
+    assert np.abs(w[3] / 1e5 - 1).max() <= 1e-10
+    assert np.abs(w[2] / 100.0 - 1).max() <= 1e-10
+
+
+def test_hll_sod_converges_and_is_more_dissipative_than_hllc():
+    errs = {0: [], 1: []}
+    for N in (100, 200, 400):
+        for riem in (0, 1):
+            c = W.sod(N)
+            c.riemann = riem
+            O = oracle.Oracle(c)
+            q = O.prim_to_cons(c.w)
+            O.run_to(q, 0.2, 0.5)
+            w = O.cons_to_prim(q)[:, 0, 0]
+            x = (np.arange(N) + 0.5) / N
+            r, u, p = er.sample((1, 0, 1), (0.125, 0, 0.1), (x - 0.5) / 0.2)
+            errs[riem].append(np.mean(np.abs(w[0] - r)))
+    assert errs[1][1] <= 4e-3
+    assert all(h > c for h, c in zip(errs[1], errs[0])), errs
+    rates = np.log2(np.array(errs[1][:-1]) / np.array(errs[1][1:]))
+    assert np.all(rates >= 0.6), rates
+
+
 def test_pressure_velocity_equilibrium_across_interface():
     """An advected air-water interface keeps p and u uniform (Allaire model)."""
     c = _case_1d_two_fluid(100)

@@ -55,7 +55,8 @@ class Case:
     cfl: float = 0.5
     t_end: float = 0.0
     weno_eps: float = 1e-6
-    weno_variant: int = 0   # 0: WENO5-JS, 1: WENO5-Z
+    weno_variant: int = 0   # 0: WENO5-JS, 1: WENO5-Z, 2: TENO5, 3: WENO5-M
+    riemann: int = 0        # 0: HLLC, 1: HLL
     extra: dict = field(default_factory=dict)
 
     @property
@@ -71,7 +72,8 @@ class Case:
         return dict(ndim=self.ndim, n=tuple(self.n), num_fluids=self.num_fluids,
                     dx=tuple(self.dx), gamma=tuple(self.gamma),
                     pi_inf=tuple(self.pi_inf), bc_lo=tuple(self.bc_lo),
-                    bc_hi=tuple(self.bc_hi), weno_eps=self.weno_eps, weno_variant=self.weno_variant)
+                    bc_hi=tuple(self.bc_hi), weno_eps=self.weno_eps, weno_variant=self.weno_variant,
+                    riemann=self.riemann)
 
 
 def _pad3(t, fill):
