@@ -237,14 +237,14 @@ def periodic_slab_leg(n=512, steps=100, warmup=2):
     return out
 
 
-def variant_grind(case, variant, steps=20, warmup=3):
+def variant_grind(case, variant, steps=20, warmup=3, riemann=0):
     """The same bubble cloud with the WENO5-Z (1) or TENO5 (2) weights of
-    Sec. 4.2.2, or the mapped WENO5-M weights (3) of Sec. 3.2.1: FP64 and
-    FP32 grind."""
+    Sec. 4.2.2, the mapped WENO5-M weights (3) of Sec. 3.2.1, or (riemann=1)
+    the HLL face solver of Sec. 3.2.2: FP64 and FP32 grind."""
     import dataclasses
 
     from paper_2503_07953_amd.solver import Solver
-    cz = dataclasses.replace(case, weno_variant=variant)
+    cz = dataclasses.replace(case, weno_variant=variant, riemann=riemann)
     out = {}
     for prec in ("fp64", "fp32"):
         S = Solver.from_case(cz, precision=prec)
@@ -353,7 +353,8 @@ def main():
         extra = {"shock_cylinder_512_fp64_ns_per_cell_stage": shock_cylinder_grind(),
                  "bubble_cloud_weno_z": variant_grind(case, 1, args.steps, args.warmup),
                  "bubble_cloud_teno5": variant_grind(case, 2, args.steps, args.warmup),
-                 "bubble_cloud_weno_m": variant_grind(case, 3, args.steps, args.warmup)}
+                 "bubble_cloud_weno_m": variant_grind(case, 3, args.steps, args.warmup),
+                 "bubble_cloud_hll": variant_grind(case, 0, args.steps, args.warmup, riemann=1)}
         log(f"extra: {extra}")
     slab = None
     if not args.no_slab:

@@ -46,7 +46,7 @@
 extern "C" {
 #endif
 
-#define MFC_ABI_VERSION 2
+#define MFC_ABI_VERSION 3
 
 enum {
   MFC_OK = 0,
@@ -85,6 +85,17 @@ enum { MFC_FP64 = 0, MFC_FP32_MIXED = 1 };
  *                there: the published fifth-order value). */
 enum { MFC_WENO_JS = 0, MFC_WENO_Z = 1, MFC_TENO = 2, MFC_WENO_M = 3 };
 
+/* Face solver (Sec. 3.2.2; Toro's book):
+ *   MFC_HLLC  three waves, star states from continuity of normal velocity and
+ *             pressure; the volume fractions ride the contact;
+ *   MFC_HLL   two waves and one averaged state, F = (S_R F_L - S_L F_R +
+ *             S_L S_R (U_R - U_L))/(S_R - S_L) between them; the volume
+ *             fractions take the same formula on alpha u_n and the face
+ *             velocity of the alpha source is (S_R u_L - S_L u_R)/(S_R - S_L)
+ *             (the paper prints no HLL formula: these are the readings).
+ *             The adjoint entry points return MFC_ERR_UNSUPPORTED for HLL. */
+enum { MFC_HLLC = 0, MFC_HLL = 1 };
+
 typedef struct {
   int32_t abi_version; /* must equal MFC_ABI_VERSION */
   int32_t ndim;        /* 1, 2 or 3 */
@@ -99,6 +110,7 @@ typedef struct {
   double pi_inf[2];    /* stiffened-gas pi_inf,i >= 0 per fluid */
   double weno_eps;     /* WENO smoothness regularization, > 0 (1e-6) */
   int32_t weno_variant; /* MFC_WENO_JS, MFC_WENO_Z, MFC_TENO or MFC_WENO_M */
+  int32_t riemann_solver; /* MFC_HLLC (0) or MFC_HLL */
 } mfc_problem;
 
 typedef struct mfc_ctx mfc_ctx;
@@ -159,7 +171,9 @@ int mfc_conserved_sums(mfc_ctx* ctx, const void* q, double* sums_dev, void* hip_
  * MFC355_ADJOINT_FACE_BUDGET (bytes, read at that first call) overrides the
  * 8 GiB threshold.
  * Outputs may not alias inputs.  accumulate != 0 adds to the output instead of
- * overwriting it. */
+ * overwriting it.  mfc_rhs_vjp, mfc_step_vjp and mfc_step_vjp_stages are
+ * written for HLLC faces: with riemann_solver = MFC_HLL they return
+ * MFC_ERR_UNSUPPORTED. */
 
 /* q_bar (+)= (dL/dq)^T rhs_bar, L the right-hand side of mfc_rhs at q. */
 int mfc_rhs_vjp(mfc_ctx* ctx, const void* q, const void* rhs_bar, void* q_bar, int accumulate,

@@ -13,8 +13,9 @@ import os
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libmfc355.so")
 
-MFC_ABI_VERSION = 2
+MFC_ABI_VERSION = 3
 MFC_WENO_JS, MFC_WENO_Z, MFC_TENO, MFC_WENO_M = 0, 1, 2, 3
+MFC_HLLC, MFC_HLL = 0, 1
 MFC_OK, MFC_ERR_ARG, MFC_ERR_SHAPE, MFC_ERR_UNSUPPORTED = 0, -1, -2, -3
 MFC_ERR_HIP, MFC_ERR_NONFINITE, MFC_ERR_ALLOC = -4, -5, -6
 MFC_BC_PERIODIC, MFC_BC_EXTRAP, MFC_BC_SLIPWALL = 0, 1, 2
@@ -35,6 +36,7 @@ class mfc_problem(ctypes.Structure):
         ("pi_inf", ctypes.c_double * 2),
         ("weno_eps", ctypes.c_double),
         ("weno_variant", ctypes.c_int32),
+        ("riemann_solver", ctypes.c_int32),
     ]
 
 
@@ -114,7 +116,7 @@ class MfcError(RuntimeError):
 
 
 def make_problem(ndim, n, num_fluids, dx, gamma, pi_inf, bc_lo, bc_hi, weno_eps=1e-6,
-                 precision=MFC_FP64, weno_variant=MFC_WENO_JS) -> mfc_problem:
+                 precision=MFC_FP64, weno_variant=MFC_WENO_JS, riemann=MFC_HLLC) -> mfc_problem:
     p = mfc_problem()
     p.abi_version = MFC_ABI_VERSION
     p.ndim = int(ndim)
@@ -131,4 +133,5 @@ def make_problem(ndim, n, num_fluids, dx, gamma, pi_inf, bc_lo, bc_hi, weno_eps=
         p.pi_inf[i] = float(pi_inf[i] if i < len(pi_inf) else pi_inf[0])
     p.weno_eps = float(weno_eps)
     p.weno_variant = int(weno_variant)
+    p.riemann_solver = int(riemann)
     return p

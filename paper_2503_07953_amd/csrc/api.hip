@@ -201,6 +201,7 @@ mfc::Params make_params(const mfc_problem& p) {
   }
   pm.eps = p.weno_eps;
   pm.weno_variant = p.weno_variant;
+  pm.riemann = p.riemann_solver;
   pm.ncell = (long long)p.n[0] * p.n[1] * p.n[2];
   return pm;
 }
@@ -259,6 +260,7 @@ int mfc_validate(const mfc_problem* p) {
     if (!(p->gamma[i] > 1.0) || !(p->pi_inf[i] >= 0.0) || !(p->pi_inf[i] < 1e300)) return MFC_ERR_ARG;
   if (!(p->weno_eps > 0.0)) return MFC_ERR_ARG;
   if (p->weno_variant < MFC_WENO_JS || p->weno_variant > MFC_WENO_M) return MFC_ERR_UNSUPPORTED;
+  if (p->riemann_solver != MFC_HLLC && p->riemann_solver != MFC_HLL) return MFC_ERR_UNSUPPORTED;
   return MFC_OK;
 }
 
@@ -488,6 +490,7 @@ int mfc_rhs_vjp(mfc_ctx* c, const void* q, const void* rhs_bar, void* q_bar, int
   if (!c) return MFC_ERR_ARG;
   if (int rd = check_device(c)) return rd;
   if (c->prob.precision != MFC_FP64) return fail(c, MFC_ERR_UNSUPPORTED, "adjoint entry points are FP64 only");
+  if (c->prob.riemann_solver != MFC_HLLC) return fail(c, MFC_ERR_UNSUPPORTED, "the adjoint is written for HLLC faces");
   int r;
   if ((r = check_array(c, q, "q")) || (r = check_array(c, rhs_bar, "rhs_bar")) || (r = check_array(c, q_bar, "q_bar")))
     return r;
@@ -503,6 +506,7 @@ int mfc_step_vjp(mfc_ctx* c, const void* q_n, double dt, const void* qnp1_bar, v
   if (!c) return MFC_ERR_ARG;
   if (int rd = check_device(c)) return rd;
   if (c->prob.precision != MFC_FP64) return fail(c, MFC_ERR_UNSUPPORTED, "adjoint entry points are FP64 only");
+  if (c->prob.riemann_solver != MFC_HLLC) return fail(c, MFC_ERR_UNSUPPORTED, "the adjoint is written for HLLC faces");
   int r;
   if ((r = check_array(c, q_n, "q_n")) || (r = check_array(c, qnp1_bar, "qnp1_bar")) ||
       (r = check_array(c, qn_bar, "qn_bar")))
@@ -554,6 +558,7 @@ int mfc_step_vjp_stages(mfc_ctx* c, const void* q_n, const void* q1, const void*
   if (!c) return MFC_ERR_ARG;
   if (int rd = check_device(c)) return rd;
   if (c->prob.precision != MFC_FP64) return fail(c, MFC_ERR_UNSUPPORTED, "adjoint entry points are FP64 only");
+  if (c->prob.riemann_solver != MFC_HLLC) return fail(c, MFC_ERR_UNSUPPORTED, "the adjoint is written for HLLC faces");
   int r;
   if ((r = check_array(c, q_n, "q_n")) || (r = check_array(c, q1, "q1")) || (r = check_array(c, q2, "q2")) ||
       (r = check_array(c, qnp1_bar, "qnp1_bar")) || (r = check_array(c, qn_bar, "qn_bar")))

@@ -19,7 +19,8 @@ struct Params {
   int n[3];            // interior cells per axis (unused axes: 1)
   int bc_lo[3];        // BC kind per axis, low side
   int bc_hi[3];        // BC kind per axis, high side
-  int weno_variant;    // 0: WENO5-JS (Sec. 3.2.1), 1: WENO5-Z, 2: TENO5 (Sec. 4.2.2)
+  int weno_variant;    // 0: WENO5-JS, 1: WENO5-Z, 2: TENO5, 3: WENO5-M
+  int riemann;         // 0: HLLC, 1: HLL (Sec. 3.2.2)
   double inv_dx[3];    // 1/dx per axis
   double G[2];         // 1/(gamma_i - 1)
   double P[2];         // gamma_i pi_inf,i/(gamma_i - 1)
@@ -552,6 +553,100 @@ __host__ __device__ __forceinline__ bool hllc(const Params& pm, const T* WL, con
 #pragma unroll
   for (int v = 0; v < R::NEQ; ++v) finite = finite && __builtin_isfinite(F[v]);
   return !(c2L > 0.0 && c2R > 0.0 && finite);
+}
+
+// ---------------------------------------------------------------------------
+// HLL face solver (Sec. 3.2.2; Toro's book): two waves, the HLLC estimates
+// S_L, S_R, and one averaged state between them.  Per face the flux is
+//   F = (a F_L + b F_R + c (U_R - U_L)) r
+// with (a, b, c, r) = (1, 0, 0, 1) for S_L >= 0, (0, 1, 0, 1) for S_R <= 0,
+// and (S_R, -S_L, S_L S_R, 1/(S_R - S_L)) otherwise; every row's U and F are
+// formed from the side's primitives as they are used.  Volume fractions take
+// the same formula on alpha u_n, and the face velocity is (a u_L + b u_R) r,
+// so that a uniform alpha stays uniform.  Returns true as hllc does.
+// ---------------------------------------------------------------------------
+template <int NF, int D, int DIR, typename T>
+__host__ __device__ __forceinline__ bool hll(const Params& pm, const T* WL, const T* WR, T* F, T& uf) {
+  using R = Rows<NF, D>;
+  T rhoL = WL[0], rhoR = WR[0];
+  if constexpr (NF == 2) {
+    rhoL = WL[0] + WL[1];
+    rhoR = WR[0] + WR[1];
+  }
+  T GamL, PiL, GamR, PiR;
+  if constexpr (NF == 2) {
+    mixture<NF, T>(pm, WL[R::ALPHA], WL[R::ALPHA + 1], GamL, PiL);
+    mixture<NF, T>(pm, WR[R::ALPHA], WR[R::ALPHA + 1], GamR, PiR);
+  } else {
+    mixture<NF, T>(pm, T(1), T(0), GamL, PiL);
+    mixture<NF, T>(pm, T(1), T(0), GamR, PiR);
+  }
+  const T pL = WL[R::E], pR = WR[R::E];
+  const T unL = WL[R::MOM + DIR], unR = WR[R::MOM + DIR];
+  const double c2L = sound_speed_sq(double(rhoL), double(pL), double(GamL), double(PiL));
+  const double c2R = sound_speed_sq(double(rhoR), double(pR), double(GamR), double(PiR));
+  const double cL = sqrt(c2L), cR = sqrt(c2R);
+  const double dunL = double(unL), dunR = double(unR);
+  const double sla = dunL - cL, slb = dunR - cR, sra = dunL + cL, srb = dunR + cR;
+  const double SL = (sla <= slb) ? sla : slb;
+  const double SR = (sra >= srb) ? sra : srb;
+  double a, b, c, r;
+  if (SL >= 0.0) {
+    a = 1.0;
+    b = 0.0;
+    c = 0.0;
+    r = 1.0;
+  } else if (SR <= 0.0) {
+    a = 0.0;
+    b = 1.0;
+    c = 0.0;
+    r = 1.0;
+  } else {
+    a = SR;
+    b = -SL;
+    c = SL * SR;
+    r = fast_rcp(SR - SL);
+  }
+  const T aT = T(a), bT = T(b), cT = T(c), rT = T(r);
+  T usqL = T(0), usqR = T(0);
+#pragma unroll
+  for (int e = 0; e < D; ++e) {
+    usqL += WL[R::MOM + e] * WL[R::MOM + e];
+    usqR += WR[R::MOM + e] * WR[R::MOM + e];
+  }
+  const T EL = GamL * pL + PiL + T(0.5) * rhoL * usqL;
+  const T ER = GamR * pR + PiR + T(0.5) * rhoR * usqR;
+#pragma unroll
+  for (int i = 0; i < NF; ++i) F[i] = (aT * (WL[i] * unL) + bT * (WR[i] * unR) + cT * (WR[i] - WL[i])) * rT;
+#pragma unroll
+  for (int e = 0; e < D; ++e) {
+    const T mL = rhoL * WL[R::MOM + e], mR = rhoR * WR[R::MOM + e];
+    const T fL = mL * unL + ((e == DIR) ? pL : T(0));
+    const T fR = mR * unR + ((e == DIR) ? pR : T(0));
+    F[R::MOM + e] = (aT * fL + bT * fR + cT * (mR - mL)) * rT;
+  }
+  F[R::E] = (aT * ((EL + pL) * unL) + bT * ((ER + pR) * unR) + cT * (ER - EL)) * rT;
+  uf = (aT * unL + bT * unR) * rT;
+  if constexpr (NF == 2) {
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+      const T aL = WL[R::ALPHA + k], aR = WR[R::ALPHA + k];
+      F[R::ALPHA + k] = (aT * (aL * unL) + bT * (aR * unR) + cT * (aR - aL)) * rT;
+    }
+  }
+  bool finite = __builtin_isfinite(uf);
+#pragma unroll
+  for (int v = 0; v < R::NEQ; ++v) finite = finite && __builtin_isfinite(F[v]);
+  return !(c2L > 0.0 && c2R > 0.0 && finite);
+}
+
+// The face solver of a kernel instantiation: RS = 0 HLLC, 1 HLL.
+template <int RS, int NF, int D, int DIR, typename T>
+__host__ __device__ __forceinline__ bool riemann(const Params& pm, const T* WL, const T* WR, T* F, T& uf) {
+  if constexpr (RS == 1)
+    return hll<NF, D, DIR, T>(pm, WL, WR, F, uf);
+  else
+    return hllc<NF, D, DIR, T>(pm, WL, WR, F, uf);
 }
 
 }  // namespace mfc

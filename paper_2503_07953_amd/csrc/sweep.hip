@@ -69,7 +69,7 @@ __device__ __forceinline__ int lds_index(int v, int s, int b) {
     return (v * TL::SA + s) * TL::TB + b;
 }
 
-template <int NF, int D, int DIR, typename Real, int MODE, int WV>
+template <int NF, int D, int DIR, typename Real, int MODE, int WV, int RS>
 __global__ __launch_bounds__((Tile<DIR, D, Real>::NT)) void sweep_kernel(Params pm, const Real* __restrict__ qk,
                                                                  Real* __restrict__ acc,
                                                                  const Real* __restrict__ qn,
@@ -255,7 +255,7 @@ __global__ __launch_bounds__((Tile<DIR, D, Real>::NT)) void sweep_kernel(Params 
     Real WL[NEQ];
 #pragma unroll
     for (int v = 0; v < NEQ; ++v) WL[v] = sh[lds_index<DIR, D, Real>(v, a - 1, b)];
-    const bool bad = hllc<NF, D, DIR, Real>(pm, WL, WRc, F, uf);
+    const bool bad = riemann<RS, NF, D, DIR, Real>(pm, WL, WRc, F, uf);
     if (bad) atomicOr(flag, 1);
   }
   __syncthreads();
@@ -309,7 +309,7 @@ __global__ __launch_bounds__((Tile<DIR, D, Real>::NT)) void sweep_kernel(Params 
 // ---------------------------------------------------------------------------
 // host launchers
 // ---------------------------------------------------------------------------
-template <int NF, int D, int DIR, typename Real, int MODE, int WV>
+template <int NF, int D, int DIR, typename Real, int MODE, int WV, int RS>
 static hipError_t launch_one(const Params& pm, const Real* qk, Real* acc, const Real* qn, Real* qout,
                              StageArgs st, int* flag, hipStream_t s, PassTimer* tm) {
   using TL = Tile<DIR, D, Real>;
@@ -327,7 +327,7 @@ static hipError_t launch_one(const Params& pm, const Real* qk, Real* acc, const 
     if (tm) tm->begin(KIND_PASS_X, s);
     for (long long base = 0; base < total && e == hipSuccess; base += kChunk) {
       const long long nb = (total - base < kChunk) ? total - base : kChunk;
-      hipLaunchKernelGGL((sweep_kernel<NF, D, DIR, Real, MODE, WV>), dim3((unsigned)nb, 1, 1), block, 0, s, pm, qk,
+      hipLaunchKernelGGL((sweep_kernel<NF, D, DIR, Real, MODE, WV, RS>), dim3((unsigned)nb, 1, 1), block, 0, s, pm, qk,
                          acc, qn, qout, st, flag, base);
       e = hipGetLastError();
     }
@@ -344,7 +344,7 @@ static hipError_t launch_one(const Params& pm, const Real* qk, Real* acc, const 
     grid = dim3((nx + TL::TB - 1) / TL::TB, ny, (nz + TL::OUT - 1) / TL::OUT);
   }
   if (tm) tm->begin(KIND_PASS_X + DIR, s);
-  hipLaunchKernelGGL((sweep_kernel<NF, D, DIR, Real, MODE, WV>), grid, block, 0, s, pm, qk, acc, qn, qout, st,
+  hipLaunchKernelGGL((sweep_kernel<NF, D, DIR, Real, MODE, WV, RS>), grid, block, 0, s, pm, qk, acc, qn, qout, st,
                      flag, 0ll);
   if (tm) tm->end(KIND_PASS_X + DIR, s);
   return hipGetLastError();
@@ -376,7 +376,7 @@ long long signal_partials(int ndim, const int* n) {
 // All axes of one RHS evaluation, z (or y) first and x last.  final_step: the
 // x pass combines into qout.  sig (2D / 3D): the first pass also forms the
 // signal-speed block maxima and dt is formed before the x pass reads it.
-template <int NF, int D, typename Real, int WV>
+template <int NF, int D, typename Real, int WV, int RS>
 static hipError_t launch_rhs_t(const Params& pm, const Real* qk, Real* acc, const Real* qn, Real* qout,
                                StageArgs st, bool final_step, int* flag, hipStream_t s, PassTimer* tm,
                                const SignalFuse* sig) {
@@ -384,34 +384,43 @@ static hipError_t launch_rhs_t(const Params& pm, const Real* qk, Real* acc, cons
   if constexpr (D == 1) {
     if (sig) return hipErrorInvalidValue;
     if (final_step)
-      e = launch_one<NF, D, 0, Real, MODE_STEP, WV>(pm, qk, acc, qn, qout, st, flag, s, tm);
+      e = launch_one<NF, D, 0, Real, MODE_STEP, WV, RS>(pm, qk, acc, qn, qout, st, flag, s, tm);
     else
-      e = launch_one<NF, D, 0, Real, MODE_WRITE, WV>(pm, qk, acc, qn, qout, st, flag, s, tm);
+      e = launch_one<NF, D, 0, Real, MODE_WRITE, WV, RS>(pm, qk, acc, qn, qout, st, flag, s, tm);
   } else {
     constexpr int FIRST = D - 1;
     if (sig) {
       StageArgs s1 = st;
       s1.sig_partial = sig->partial;
-      e = launch_one<NF, D, FIRST, Real, MODE_WRITE | MODE_SIGNAL, WV>(pm, qk, acc, qn, qout, s1, flag, s, tm);
+      e = launch_one<NF, D, FIRST, Real, MODE_WRITE | MODE_SIGNAL, WV, RS>(pm, qk, acc, qn, qout, s1, flag, s, tm);
       if (e != hipSuccess) return e;
       if (tm) tm->begin(KIND_SIGNAL, s);
       e = launch_finalize_dt(sig->partial, (int)first_pass_blocks<D, Real>(pm.n), sig->cfl, sig->t_remaining,
                              sig->smax_out, sig->dt_out, sig->dt_user, s);
       if (tm) tm->end(KIND_SIGNAL, s);
     } else {
-      e = launch_one<NF, D, FIRST, Real, MODE_WRITE, WV>(pm, qk, acc, qn, qout, st, flag, s, tm);
+      e = launch_one<NF, D, FIRST, Real, MODE_WRITE, WV, RS>(pm, qk, acc, qn, qout, st, flag, s, tm);
     }
     if (e != hipSuccess) return e;
     if constexpr (D == 3) {
-      e = launch_one<NF, D, 1, Real, MODE_ACC, WV>(pm, qk, acc, qn, qout, st, flag, s, tm);
+      e = launch_one<NF, D, 1, Real, MODE_ACC, WV, RS>(pm, qk, acc, qn, qout, st, flag, s, tm);
       if (e != hipSuccess) return e;
     }
     if (final_step)
-      e = launch_one<NF, D, 0, Real, MODE_ACC | MODE_STEP, WV>(pm, qk, acc, qn, qout, st, flag, s, tm);
+      e = launch_one<NF, D, 0, Real, MODE_ACC | MODE_STEP, WV, RS>(pm, qk, acc, qn, qout, st, flag, s, tm);
     else
-      e = launch_one<NF, D, 0, Real, MODE_ACC, WV>(pm, qk, acc, qn, qout, st, flag, s, tm);
+      e = launch_one<NF, D, 0, Real, MODE_ACC, WV, RS>(pm, qk, acc, qn, qout, st, flag, s, tm);
   }
   return e;
+}
+
+// The face solver is a compile-time choice too (a run-time branch would make
+// every kernel hold the registers of both).
+template <int NF, int D, typename Real, int WV>
+static hipError_t by_riemann(const Params& pm, const Real* qk, Real* acc, const Real* qn, Real* qout, StageArgs st,
+                             bool final_step, int* flag, hipStream_t s, PassTimer* tm, const SignalFuse* sig) {
+  if (pm.riemann == 1) return launch_rhs_t<NF, D, Real, WV, 1>(pm, qk, acc, qn, qout, st, final_step, flag, s, tm, sig);
+  return launch_rhs_t<NF, D, Real, WV, 0>(pm, qk, acc, qn, qout, st, final_step, flag, s, tm, sig);
 }
 
 template <typename Real>
@@ -421,10 +430,10 @@ hipError_t launch_rhs(int nf, int ndim, const Params& pm, const Real* qk, Real* 
 #define MFC_ARGS pm, qk, acc, qn, qout, st, final_step, flag, s, tm, sig
 #define MFC_CASE(NF, D)                                                        \
   if (nf == NF && ndim == D)                                                   \
-    return pm.weno_variant == 1   ? launch_rhs_t<NF, D, Real, 1>(MFC_ARGS)     \
-           : pm.weno_variant == 2 ? launch_rhs_t<NF, D, Real, 2>(MFC_ARGS)     \
-           : pm.weno_variant == 3 ? launch_rhs_t<NF, D, Real, 3>(MFC_ARGS)     \
-                                  : launch_rhs_t<NF, D, Real, 0>(MFC_ARGS);
+    return pm.weno_variant == 1   ? by_riemann<NF, D, Real, 1>(MFC_ARGS)       \
+           : pm.weno_variant == 2 ? by_riemann<NF, D, Real, 2>(MFC_ARGS)       \
+           : pm.weno_variant == 3 ? by_riemann<NF, D, Real, 3>(MFC_ARGS)       \
+                                  : by_riemann<NF, D, Real, 0>(MFC_ARGS);
   MFC_CASE(1, 1)
   MFC_CASE(1, 2)
   MFC_CASE(1, 3)

@@ -71,6 +71,9 @@ def test_num_eqs(L):
     (dict(weno_variant=3), 0),
     (dict(weno_variant=4), -3),
     (dict(weno_variant=-1), -3),
+    (dict(riemann=1), 0),
+    (dict(riemann=2), -3),
+    (dict(riemann=-1), -3),
 ])
 def test_validation_codes(L, kw, code):
     lib = L.load()

@@ -184,6 +184,44 @@ def test_weno_variants_two_fluid_flows_match_oracle(name, variant):
     _variant_steps_match(c, 2, c.ndim, flux_scale=True)
 
 
+@pytest.mark.parametrize("case", [CASES[0], CASES[1], CASES[3], CASES[5], CASES[6], CASES[7]])
+def test_hll_rhs_and_steps_match_oracle(case):
+    """The HLL face solver (Sec. 3.2.2) through the same kernels."""
+    nd, n, nf, bc = case
+    _say("hll", nd, n, nf, bc)
+    c = W.random_case(nd, n, nf=nf, seed=600 + nd, bc=bc, speed=400.0 if nf == 1 else 150.0)
+    c.riemann = 1
+    _variant_steps_match(c, nf, nd)
+
+
+@pytest.mark.parametrize("name", ["shock-cylinder-96", "bubble-cloud-64"])
+def test_hll_two_fluid_flows_match_oracle(name):
+    _say("hll", name)
+    c = W.shock_cylinder(96) if name.startswith("shock") else W.bubble_cloud(64, nbub=6, slab=8)
+    c.riemann = 1
+    _variant_steps_match(c, 2, c.ndim, flux_scale=True)
+
+
+def test_hll_differs_from_hllc_and_has_no_adjoint():
+    from paper_2503_07953_amd import _lib as L
+    c = W.random_case(2, (40, 30), nf=2, seed=9, bc=(W.EXTRAP, W.PERIODIC))
+    O = oracle.Oracle(c)
+    q = O.prim_to_cons(c.w)
+    S0 = _solver(c)
+    r0 = S0.rhs(S0.to_device(q)).cpu().numpy()
+    c.riemann = 1
+    S1 = _solver(c)
+    qd = S1.to_device(q)
+    r1 = S1.rhs(qd).cpu().numpy()
+    assert not np.array_equal(r0, r1)
+    with pytest.raises(L.MfcError) as e:
+        S1.rhs_vjp(qd, torch.ones_like(qd))
+    assert e.value.code == L.MFC_ERR_UNSUPPORTED
+    with pytest.raises(L.MfcError) as e:
+        S1.step_vjp(qd, 1e-7, torch.ones_like(qd))
+    assert e.value.code == L.MFC_ERR_UNSUPPORTED
+
+
 def test_teno_rough_two_fluid_flagged_on_both_sides():
     """Two-fluid white noise under TENO5 reconstructs a face state with c^2 <= 0;
     the oracle refuses it and the library's check reports MFC_ERR_NONFINITE."""
