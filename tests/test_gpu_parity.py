@@ -222,6 +222,40 @@ def test_hll_differs_from_hllc_and_has_no_adjoint():
     assert e.value.code == L.MFC_ERR_UNSUPPORTED
 
 
+@pytest.mark.slow
+def test_hll_bubble_cloud_breaks_down_at_the_oracles_step():
+    """Under HLL (with its alpha reading) the 100 bar pulse through the 64^3
+    bubble cloud reaches a face state with c^2 <= 0 after 67 good CFL steps;
+    HLLC passes those steps.  The library must report MFC_ERR_NONFINITE at the
+    very step the oracle refuses, and not before."""
+    from paper_2503_07953_amd import _lib as L
+    c = W.bubble_cloud(64, nbub=6, slab=8)
+    c.riemann = 1
+    O = oracle.Oracle(c)
+    q = O.prim_to_cons(c.w)
+    k_oracle = None
+    for k in range(80):
+        try:
+            O.step(q, cfl=0.5)
+        except oracle.OracleError:
+            k_oracle = k
+            break
+    assert k_oracle is not None
+    S = _solver(c)
+    qd = S.prim_to_cons(S.to_device(c.w))
+    k_lib = None
+    for k in range(80):
+        S.step(qd, cfl=0.5)
+        try:
+            S.check()
+        except L.MfcError as e:
+            assert e.code == L.MFC_ERR_NONFINITE
+            k_lib = k
+            break
+    _say("hll breakdown step: oracle", k_oracle, "library", k_lib)
+    assert k_lib == k_oracle
+
+
 def test_teno_rough_two_fluid_flagged_on_both_sides():
     """Two-fluid white noise under TENO5 reconstructs a face state with c^2 <= 0;
     the oracle refuses it and the library's check reports MFC_ERR_NONFINITE."""
