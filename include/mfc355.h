@@ -92,8 +92,7 @@ enum { MFC_WENO_JS = 0, MFC_WENO_Z = 1, MFC_TENO = 2, MFC_WENO_M = 3 };
  *             S_L S_R (U_R - U_L))/(S_R - S_L) between them; the volume
  *             fractions take the same formula on alpha u_n and the face
  *             velocity of the alpha source is (S_R u_L - S_L u_R)/(S_R - S_L)
- *             (the paper prints no HLL formula: these are the readings).
- *             The adjoint entry points return MFC_ERR_UNSUPPORTED for HLL. */
+ *             (the paper prints no HLL formula: these are the readings). */
 enum { MFC_HLLC = 0, MFC_HLL = 1 };
 
 typedef struct {
@@ -171,9 +170,8 @@ int mfc_conserved_sums(mfc_ctx* ctx, const void* q, double* sums_dev, void* hip_
  * MFC355_ADJOINT_FACE_BUDGET (bytes, read at that first call) overrides the
  * 8 GiB threshold.
  * Outputs may not alias inputs.  accumulate != 0 adds to the output instead of
- * overwriting it.  mfc_rhs_vjp, mfc_step_vjp and mfc_step_vjp_stages are
- * written for HLLC faces: with riemann_solver = MFC_HLL they return
- * MFC_ERR_UNSUPPORTED. */
+ * overwriting it.  Both face solvers (HLLC, HLL) have their hand-written
+ * adjoint. */
 
 /* q_bar (+)= (dL/dq)^T rhs_bar, L the right-hand side of mfc_rhs at q. */
 int mfc_rhs_vjp(mfc_ctx* ctx, const void* q, const void* rhs_bar, void* q_bar, int accumulate,

@@ -574,4 +574,156 @@ __host__ __device__ __forceinline__ void hllc_vjp(const Params& pm, const double
                                useL ? 0.0 : Eb, cRb, WRb);
 }
 
+// ---------------------------------------------------------------------------
+// HLL adjoint (same readings as hll()).  Forward, per face:
+//   F_v = N_v r, N_v = a F_L,v + b F_R,v + c (U_R,v - U_L,v), u_f = (a u_L + b u_R) r,
+// (a, b, c, r) = (1, 0, 0, 1) | (0, 1, 0, 1) | (S_R, -S_L, S_L S_R, 1/(S_R - S_L)).
+// With G_v = Fbar_v r the sides receive Fbar_L = a G, Fbar_R = b G,
+// Ubar_R = c G, Ubar_L = -c G; between the waves the coefficients add
+//   abar = sum G F_L + ufbar r u_L, bbar = sum G F_R + ufbar r u_R,
+//   cbar = sum G (U_R - U_L), rbar = sum Fbar N + ufbar (a u_L + b u_R),
+//   S_R bar = abar + cbar S_L - rbar r^2, S_L bar = -bbar + cbar S_R + rbar r^2,
+// which reach u and c of the side each min / max took (ties: first).
+// Accumulates WLbar, WRbar; uf_out (optional) receives the forward u_f.
+// ---------------------------------------------------------------------------
+template <int NF, int D, int DIR>
+__host__ __device__ __forceinline__ void hll_side_rows_vjp(const double* W, const SideState<NF, D>& s,
+                                                          const double* Fb, const double* Ub, double& rhob,
+                                                          double& pb, double& unb, double& Eb, double* Wb) {
+  using R = Rows<NF, D>;
+#pragma unroll
+  for (int i = 0; i < NF; ++i) {
+    Wb[i] += Fb[i] * s.un + Ub[i];
+    unb += Fb[i] * W[i];
+  }
+#pragma unroll
+  for (int e = 0; e < D; ++e) {
+    const double m = s.rho * W[R::MOM + e];
+    const double mb = Fb[R::MOM + e] * s.un + Ub[R::MOM + e];
+    unb += Fb[R::MOM + e] * m;
+    if (e == DIR) pb += Fb[R::MOM + e];
+    rhob += mb * W[R::MOM + e];
+    Wb[R::MOM + e] += mb * s.rho;
+  }
+  Eb += Fb[R::E] * s.un + Ub[R::E];
+  pb += Fb[R::E] * s.un;
+  unb += Fb[R::E] * (s.E + s.p);
+  if constexpr (NF == 2) {
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      Wb[R::ALPHA + j] += Fb[R::ALPHA + j] * s.un + Ub[R::ALPHA + j];
+      unb += Fb[R::ALPHA + j] * W[R::ALPHA + j];
+    }
+  }
+}
+
+template <int NF, int D, int DIR>
+__host__ __device__ __forceinline__ void hll_vjp(const Params& pm, const double* WL, const double* WR,
+                                                 const double* Fb, double ufb, double* WLb, double* WRb,
+                                                 double* uf_out = nullptr) {
+  using R = Rows<NF, D>;
+  constexpr int NEQ = R::NEQ;
+  SideState<NF, D> L, Rs;
+  side_state<NF, D, DIR>(pm, WL, L);
+  side_state<NF, D, DIR>(pm, WR, Rs);
+  const double sla = L.un - L.c, slb = Rs.un - Rs.c, sra = L.un + L.c, srb = Rs.un + Rs.c;
+  const bool sl_left = sla <= slb;
+  const bool sr_left = sra >= srb;
+  const double SL = sl_left ? sla : slb;
+  const double SR = sr_left ? sra : srb;
+  const bool lo = SL >= 0.0, hi = !lo && SR <= 0.0, mid = !lo && !hi;
+  double a = 1.0, b = 0.0, c = 0.0, r = 1.0;
+  if (hi) {
+    a = 0.0;
+    b = 1.0;
+  } else if (mid) {
+    a = SR;
+    b = -SL;
+    c = SL * SR;
+    r = fast_rcp(SR - SL);
+  }
+  if (uf_out) *uf_out = (a * L.un + b * Rs.un) * r;
+  // per-row physical fluxes and conservative values of both sides
+  double FL[NEQ], FR[NEQ], UL[NEQ], UR[NEQ];
+#pragma unroll
+  for (int i = 0; i < NF; ++i) {
+    UL[i] = WL[i];
+    UR[i] = WR[i];
+    FL[i] = WL[i] * L.un;
+    FR[i] = WR[i] * Rs.un;
+  }
+#pragma unroll
+  for (int e = 0; e < D; ++e) {
+    UL[R::MOM + e] = L.rho * WL[R::MOM + e];
+    UR[R::MOM + e] = Rs.rho * WR[R::MOM + e];
+    FL[R::MOM + e] = UL[R::MOM + e] * L.un + ((e == DIR) ? L.p : 0.0);
+    FR[R::MOM + e] = UR[R::MOM + e] * Rs.un + ((e == DIR) ? Rs.p : 0.0);
+  }
+  UL[R::E] = L.E;
+  UR[R::E] = Rs.E;
+  FL[R::E] = (L.E + L.p) * L.un;
+  FR[R::E] = (Rs.E + Rs.p) * Rs.un;
+  if constexpr (NF == 2) {
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      UL[R::ALPHA + j] = WL[R::ALPHA + j];
+      UR[R::ALPHA + j] = WR[R::ALPHA + j];
+      FL[R::ALPHA + j] = WL[R::ALPHA + j] * L.un;
+      FR[R::ALPHA + j] = WR[R::ALPHA + j] * Rs.un;
+    }
+  }
+  double FLb[NEQ], FRb[NEQ], ULb[NEQ], URb[NEQ];
+  double ab = ufb * r * L.un, bb = ufb * r * Rs.un, cb = 0.0, rb = ufb * (a * L.un + b * Rs.un);
+#pragma unroll
+  for (int v = 0; v < NEQ; ++v) {
+    const double G = Fb[v] * r;
+    const double dU = UR[v] - UL[v];
+    FLb[v] = a * G;
+    FRb[v] = b * G;
+    URb[v] = c * G;
+    ULb[v] = -c * G;
+    ab += G * FL[v];
+    bb += G * FR[v];
+    cb += G * dU;
+    rb += Fb[v] * (a * FL[v] + b * FR[v] + c * dU);
+  }
+  double unLb = ufb * r * a, unRb = ufb * r * b;
+  double cLb = 0.0, cRb = 0.0;
+  if (mid) {
+    const double r2 = r * r;
+    const double SRb = ab + cb * SL - rb * r2;
+    const double SLb = -bb + cb * SR + rb * r2;
+    if (sl_left) {
+      unLb += SLb;
+      cLb -= SLb;
+    } else {
+      unRb += SLb;
+      cRb -= SLb;
+    }
+    if (sr_left) {
+      unLb += SRb;
+      cLb += SRb;
+    } else {
+      unRb += SRb;
+      cRb += SRb;
+    }
+  }
+  double rhoLb = 0.0, pLb = 0.0, ELb = 0.0, rhoRb = 0.0, pRb = 0.0, ERb = 0.0;
+  hll_side_rows_vjp<NF, D, DIR>(WL, L, FLb, ULb, rhoLb, pLb, unLb, ELb, WLb);
+  hll_side_rows_vjp<NF, D, DIR>(WR, Rs, FRb, URb, rhoRb, pRb, unRb, ERb, WRb);
+  side_scalars_vjp<NF, D, DIR>(pm, WL, L, rhoLb, 0.0, 0.0, pLb, unLb, ELb, cLb, WLb);
+  side_scalars_vjp<NF, D, DIR>(pm, WR, Rs, rhoRb, 0.0, 0.0, pRb, unRb, ERb, cRb, WRb);
+}
+
+// The face-solver adjoint of a kernel instantiation: RS = 0 HLLC, 1 HLL.
+template <int RS, int NF, int D, int DIR>
+__host__ __device__ __forceinline__ void riemann_vjp(const Params& pm, const double* WL, const double* WR,
+                                                     const double* Fb, double ufb, double* WLb, double* WRb,
+                                                     double* uf_out = nullptr) {
+  if constexpr (RS == 1)
+    hll_vjp<NF, D, DIR>(pm, WL, WR, Fb, ufb, WLb, WRb, uf_out);
+  else
+    hllc_vjp<NF, D, DIR>(pm, WL, WR, Fb, ufb, WLb, WRb, uf_out);
+}
+
 }  // namespace mfc

@@ -490,7 +490,6 @@ int mfc_rhs_vjp(mfc_ctx* c, const void* q, const void* rhs_bar, void* q_bar, int
   if (!c) return MFC_ERR_ARG;
   if (int rd = check_device(c)) return rd;
   if (c->prob.precision != MFC_FP64) return fail(c, MFC_ERR_UNSUPPORTED, "adjoint entry points are FP64 only");
-  if (c->prob.riemann_solver != MFC_HLLC) return fail(c, MFC_ERR_UNSUPPORTED, "the adjoint is written for HLLC faces");
   int r;
   if ((r = check_array(c, q, "q")) || (r = check_array(c, rhs_bar, "rhs_bar")) || (r = check_array(c, q_bar, "q_bar")))
     return r;
@@ -506,7 +505,6 @@ int mfc_step_vjp(mfc_ctx* c, const void* q_n, double dt, const void* qnp1_bar, v
   if (!c) return MFC_ERR_ARG;
   if (int rd = check_device(c)) return rd;
   if (c->prob.precision != MFC_FP64) return fail(c, MFC_ERR_UNSUPPORTED, "adjoint entry points are FP64 only");
-  if (c->prob.riemann_solver != MFC_HLLC) return fail(c, MFC_ERR_UNSUPPORTED, "the adjoint is written for HLLC faces");
   int r;
   if ((r = check_array(c, q_n, "q_n")) || (r = check_array(c, qnp1_bar, "qnp1_bar")) ||
       (r = check_array(c, qn_bar, "qn_bar")))
@@ -558,7 +556,6 @@ int mfc_step_vjp_stages(mfc_ctx* c, const void* q_n, const void* q1, const void*
   if (!c) return MFC_ERR_ARG;
   if (int rd = check_device(c)) return rd;
   if (c->prob.precision != MFC_FP64) return fail(c, MFC_ERR_UNSUPPORTED, "adjoint entry points are FP64 only");
-  if (c->prob.riemann_solver != MFC_HLLC) return fail(c, MFC_ERR_UNSUPPORTED, "the adjoint is written for HLLC faces");
   int r;
   if ((r = check_array(c, q_n, "q_n")) || (r = check_array(c, q1, "q1")) || (r = check_array(c, q2, "q2")) ||
       (r = check_array(c, qnp1_bar, "qnp1_bar")) || (r = check_array(c, qn_bar, "qn_bar")))

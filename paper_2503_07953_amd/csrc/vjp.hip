@@ -99,7 +99,7 @@ __host__ __device__ __forceinline__ void face_grid(const int* n, int& g0, int& g
 // One face tile of axis DIR (tile coordinates t0, t1, t2 as in face_grid):
 // face cotangents, HLLC^T and WENO^T, writing the six stencil positions'
 // primitive cotangents of every face to G and the forward face velocity to UF.
-template <int NF, int D, int DIR, int WV>
+template <int NF, int D, int DIR, int WV, int RS>
 __device__ __forceinline__ void face_tile(const Params pm, const double* __restrict__ q,
                                           const double* __restrict__ rbar, double* __restrict__ G,
                                           double* __restrict__ UF, const AxisGeom& fg, int t0, int t1, int t2,
@@ -198,7 +198,7 @@ __device__ __forceinline__ void face_tile(const Params pm, const double* __restr
 #pragma unroll
   for (int v = 0; v < NEQ; ++v) WLb[v] = WRb[v] = 0.0;
   double uf;
-  hllc_vjp<NF, D, DIR>(pm, WL, WR, Fb, ufb, WLb, WRb, &uf);
+  riemann_vjp<RS, NF, D, DIR>(pm, WL, WR, Fb, ufb, WLb, WRb, &uf);
 
   const long long nfc = fg.count;
   // compiler-only memory barrier: the stencil values are read from LDS again
@@ -250,19 +250,19 @@ __device__ __forceinline__ void unflatten_tile(int w, const Params& pm, int& t0,
 }
 
 // Face pass of one axis (sequential path).
-template <int NF, int D, int DIR, int WV>
+template <int NF, int D, int DIR, int WV, int RS>
 __global__ __launch_bounds__(kFaceThreads) void vjp_face_kernel(Params pm, const double* __restrict__ q,
                                                                const double* __restrict__ rbar,
                                                                double* __restrict__ G, double* __restrict__ UF) {
   __shared__ double sw[FaceLds<Rows<NF, D>::NEQ>::size];
   int t0, t1, t2;
   unflatten_tile<DIR>(blockIdx.x, pm, t0, t1, t2);
-  face_tile<NF, D, DIR, WV>(pm, q, rbar, G, UF, face_geom<DIR>(pm), t0, t1, t2, threadIdx.x, sw);
+  face_tile<NF, D, DIR, WV, RS>(pm, q, rbar, G, UF, face_geom<DIR>(pm), t0, t1, t2, threadIdx.x, sw);
 }
 
 // Face passes of every axis in one launch: blocks [0, nb[0]) take x tiles,
 // the next nb[1] y tiles, then z.  Each axis writes its own G and UF.
-template <int NF, int D, int WV>
+template <int NF, int D, int WV, int RS>
 __global__ __launch_bounds__(kFaceThreads) void vjp_faces_all_kernel(Params pm, const double* __restrict__ q,
                                                                     const double* __restrict__ rbar, VjpScratch sc,
                                                                     int nb0, int nb1) {
@@ -270,21 +270,21 @@ __global__ __launch_bounds__(kFaceThreads) void vjp_faces_all_kernel(Params pm, 
   int w = blockIdx.x, t0, t1, t2;
   if (w < nb0) {
     unflatten_tile<0>(w, pm, t0, t1, t2);
-    face_tile<NF, D, 0, WV>(pm, q, rbar, sc.Gd[0], sc.UFd[0], face_geom<0>(pm), t0, t1, t2, threadIdx.x, sw);
+    face_tile<NF, D, 0, WV, RS>(pm, q, rbar, sc.Gd[0], sc.UFd[0], face_geom<0>(pm), t0, t1, t2, threadIdx.x, sw);
     return;
   }
   w -= nb0;
   if constexpr (D > 1) {
     if (w < nb1) {
       unflatten_tile<1>(w, pm, t0, t1, t2);
-      face_tile<NF, D, 1, WV>(pm, q, rbar, sc.Gd[1], sc.UFd[1], face_geom<1>(pm), t0, t1, t2, threadIdx.x, sw);
+      face_tile<NF, D, 1, WV, RS>(pm, q, rbar, sc.Gd[1], sc.UFd[1], face_geom<1>(pm), t0, t1, t2, threadIdx.x, sw);
       return;
     }
     w -= nb1;
   }
   if constexpr (D > 2) {
     unflatten_tile<2>(w, pm, t0, t1, t2);
-    face_tile<NF, D, 2, WV>(pm, q, rbar, sc.Gd[2], sc.UFd[2], face_geom<2>(pm), t0, t1, t2, threadIdx.x, sw);
+    face_tile<NF, D, 2, WV, RS>(pm, q, rbar, sc.Gd[2], sc.UFd[2], face_geom<2>(pm), t0, t1, t2, threadIdx.x, sw);
   }
 }
 
@@ -397,10 +397,10 @@ static int face_blocks(const Params& pm) {
 
 // Sequential path: per axis, its face pass into the shared buffer Gd[0] /
 // UFd[0], then its cell pass.
-template <int NF, int D, int DIR, int WV>
+template <int NF, int D, int DIR, int WV, int RS>
 static hipError_t launch_axis_vjp(const Params& pm, const double* q, const double* rbar, double* qbar,
                                   VjpScratch sc, bool accumulate, hipStream_t s) {
-  hipLaunchKernelGGL((vjp_face_kernel<NF, D, DIR, WV>), dim3((unsigned)face_blocks<DIR>(pm)), dim3(kFaceThreads), 0, s,
+  hipLaunchKernelGGL((vjp_face_kernel<NF, D, DIR, WV, RS>), dim3((unsigned)face_blocks<DIR>(pm)), dim3(kFaceThreads), 0, s,
                      pm, q, rbar, sc.Gd[0], sc.UFd[0]);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
@@ -413,7 +413,7 @@ static hipError_t launch_axis_vjp(const Params& pm, const double* q, const doubl
   return hipGetLastError();
 }
 
-template <int NF, int D, int WV>
+template <int NF, int D, int WV, int RS>
 static hipError_t launch_rhs_vjp_t(const Params& pm, const double* q, const double* rbar, double* qbar,
                                    const VjpScratch& sc, bool accumulate, hipStream_t s, PassTimer* tm) {
   hipError_t e = hipSuccess;
@@ -423,7 +423,7 @@ static hipError_t launch_rhs_vjp_t(const Params& pm, const double* q, const doub
     const int nb0 = face_blocks<0>(pm);
     const int nb1 = D > 1 ? face_blocks<(D > 1 ? 1 : 0)>(pm) : 0;
     const int nb2 = D > 2 ? face_blocks<(D > 2 ? 2 : 0)>(pm) : 0;
-    hipLaunchKernelGGL((vjp_faces_all_kernel<NF, D, WV>), dim3((unsigned)(nb0 + nb1 + nb2)), dim3(kFaceThreads), 0, s, pm,
+    hipLaunchKernelGGL((vjp_faces_all_kernel<NF, D, WV, RS>), dim3((unsigned)(nb0 + nb1 + nb2)), dim3(kFaceThreads), 0, s, pm,
                        q, rbar, sc, nb0, nb1);
     e = hipGetLastError();
     if (e == hipSuccess) {
@@ -432,22 +432,30 @@ static hipError_t launch_rhs_vjp_t(const Params& pm, const double* q, const doub
       e = hipGetLastError();
     }
   } else {
-    e = launch_axis_vjp<NF, D, 0, WV>(pm, q, rbar, qbar, sc, accumulate, s);
-    if (e == hipSuccess && D > 1) e = launch_axis_vjp<NF, D, (D > 1 ? 1 : 0), WV>(pm, q, rbar, qbar, sc, true, s);
-    if (e == hipSuccess && D > 2) e = launch_axis_vjp<NF, D, (D > 2 ? 2 : 0), WV>(pm, q, rbar, qbar, sc, true, s);
+    e = launch_axis_vjp<NF, D, 0, WV, RS>(pm, q, rbar, qbar, sc, accumulate, s);
+    if (e == hipSuccess && D > 1) e = launch_axis_vjp<NF, D, (D > 1 ? 1 : 0), WV, RS>(pm, q, rbar, qbar, sc, true, s);
+    if (e == hipSuccess && D > 2) e = launch_axis_vjp<NF, D, (D > 2 ? 2 : 0), WV, RS>(pm, q, rbar, qbar, sc, true, s);
   }
   if (tm) tm->end(KIND_VJP, s);
   return e;
+}
+
+// The face solver is a compile-time choice, as in the forward passes.
+template <int NF, int D, int WV>
+static hipError_t vjp_by_riemann(const Params& pm, const double* q, const double* rbar, double* qbar,
+                                 const VjpScratch& sc, bool accumulate, hipStream_t s, PassTimer* tm) {
+  if (pm.riemann == 1) return launch_rhs_vjp_t<NF, D, WV, 1>(pm, q, rbar, qbar, sc, accumulate, s, tm);
+  return launch_rhs_vjp_t<NF, D, WV, 0>(pm, q, rbar, qbar, sc, accumulate, s, tm);
 }
 
 hipError_t launch_rhs_vjp(int nf, int ndim, const Params& pm, const double* q, const double* rbar, double* qbar,
                           const VjpScratch& sc, bool accumulate, hipStream_t s, PassTimer* tm) {
 #define MFC_CASE(NF, D)                                                                   \
   if (nf == NF && ndim == D)                                                              \
-    return pm.weno_variant == 1   ? launch_rhs_vjp_t<NF, D, 1>(pm, q, rbar, qbar, sc, accumulate, s, tm) \
-           : pm.weno_variant == 2 ? launch_rhs_vjp_t<NF, D, 2>(pm, q, rbar, qbar, sc, accumulate, s, tm) \
-           : pm.weno_variant == 3 ? launch_rhs_vjp_t<NF, D, 3>(pm, q, rbar, qbar, sc, accumulate, s, tm) \
-                                  : launch_rhs_vjp_t<NF, D, 0>(pm, q, rbar, qbar, sc, accumulate, s, tm);
+    return pm.weno_variant == 1   ? vjp_by_riemann<NF, D, 1>(pm, q, rbar, qbar, sc, accumulate, s, tm) \
+           : pm.weno_variant == 2 ? vjp_by_riemann<NF, D, 2>(pm, q, rbar, qbar, sc, accumulate, s, tm) \
+           : pm.weno_variant == 3 ? vjp_by_riemann<NF, D, 3>(pm, q, rbar, qbar, sc, accumulate, s, tm) \
+                                  : vjp_by_riemann<NF, D, 0>(pm, q, rbar, qbar, sc, accumulate, s, tm);
   MFC_CASE(1, 1)
   MFC_CASE(1, 2)
   MFC_CASE(1, 3)

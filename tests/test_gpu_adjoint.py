@@ -53,6 +53,21 @@ def test_rhs_vjp_matches_reference_autograd(nd, n, nf, bc, variant):
     _say("rhs_vjp", nd, n, nf, bc, "variant", variant)
     c = W.random_case(nd, n, nf=nf, seed=40 + nd, bc=bc, speed=300.0 if nf == 1 else 150.0)
     c.weno_variant = variant
+    _rhs_vjp_vs_autograd(c)
+
+
+@pytest.mark.parametrize("nd,n,nf,bc", [CASES[0], CASES[2], CASES[4], CASES[5]])
+def test_hll_rhs_vjp_matches_reference_autograd(nd, n, nf, bc):
+    """The HLL face solver's hand-written adjoint against autograd of the
+    torch reference."""
+    _say("hll rhs_vjp", nd, n, nf, bc)
+    c = W.random_case(nd, n, nf=nf, seed=45 + nd, bc=bc, speed=300.0 if nf == 1 else 150.0)
+    c.riemann = 1
+    _rhs_vjp_vs_autograd(c)
+
+
+def _rhs_vjp_vs_autograd(c):
+    nd, nf = c.ndim, c.num_fluids
     O = oracle.Oracle(c)
     q = O.prim_to_cons(c.w)
     P = TR.Problem.from_case(c)
