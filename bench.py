@@ -237,6 +237,33 @@ def periodic_slab_leg(n=512, steps=100, warmup=2):
     return out
 
 
+def paper_shape_grind(steps=20, warmup=3):
+    """The paper's single-device benchmark shape (Sec. 5: 3D, two fluids, 8
+    PDEs) at 158^3 and 200^3 cells, from the bubble-cloud generator (seed 5):
+    FP64 and FP32 grind, also per PDE (the paper's unit), each the median of
+    three runs of warmup + steps CFL steps from the initial state."""
+    import workloads as W
+    from paper_2503_07953_amd.solver import Solver
+    out = {}
+    for n in (158, 200):
+        c = W.bubble_cloud(n, seed=5)
+        row = {}
+        for prec in ("fp64", "fp32"):
+            S = Solver.from_case(c, precision=prec)
+            reps = []
+            for _ in range(3):
+                q = S.prim_to_cons(S.to_device(c.w))
+                ms, _, _ = time_steps(S, q, steps, warmup, c.cfl, kernel_steps=0, repeats=1)
+                reps.append(ms)
+                del q
+            g = sorted(reps)[1] / steps * 1e6 / (c.ncell * 3)
+            row[f"{prec}_ns_per_cell_stage"] = round(g, 5)
+            row[f"{prec}_ns_per_pde_stage"] = round(g / 8, 6)
+            del S
+        out[f"{n}^3"] = row
+    return out
+
+
 def variant_grind(case, variant, steps=20, warmup=3, riemann=0):
     """The same bubble cloud with the WENO5-Z (1) or TENO5 (2) weights of
     Sec. 4.2.2, the mapped WENO5-M weights (3) of Sec. 3.2.1, or (riemann=1)
@@ -284,7 +311,9 @@ def main():
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
-    ap.add_argument("--no-extra", action="store_true", help="skip the 512^2 shock-cylinder grind time")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="skip the other workloads (512^2 shock cylinder, reconstruction and face-solver variants, "
+                         "the paper's 158^3 / 200^3 benchmark shape)")
     ap.add_argument("--no-slab", action="store_true", help="skip the 512^3 periodic-slab FP32/FP64 leg")
     ap.add_argument("--slab-n", type=int, default=512)
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -360,7 +389,8 @@ def main():
                  "bubble_cloud_weno_z": variant_grind(case, 1, args.steps, args.warmup),
                  "bubble_cloud_teno5": variant_grind(case, 2, args.steps, args.warmup),
                  "bubble_cloud_weno_m": variant_grind(case, 3, args.steps, args.warmup),
-                 "bubble_cloud_hll": variant_grind(case, 0, args.steps, args.warmup, riemann=1)}
+                 "bubble_cloud_hll": variant_grind(case, 0, args.steps, args.warmup, riemann=1),
+                 "paper_benchmark_shape": paper_shape_grind(args.steps, args.warmup)}
         log(f"extra: {extra}")
     slab = None
     if not args.no_slab:
@@ -378,9 +408,15 @@ def main():
         O.step(qh, cfl=cfl)
         t_cpu = time.time() - t0
         threads = oracle.num_threads()
+        model = "unknown CPU"
+        try:
+            with open("/proc/cpuinfo") as f:
+                model = next(l.split(":", 1)[1].strip() for l in f if l.startswith("model name"))
+        except (OSError, StopIteration):
+            pass
         cpu = {"value": round(t_cpu * 1e9 / (ncell * 3), 3), "unit": "ns/cell/RK-stage", "cores": threads,
                "kind": "oracle", "sample": f"1 SSP-RK3 step (3 RHS evaluations) of the {args.n}^3 bubble cloud, "
-                                           f"{t_cpu:.1f} s wall on {threads} OpenMP threads"}
+                                           f"{t_cpu:.1f} s wall on {threads} OpenMP threads ({model})"}
         log(f"cpu oracle: {cpu}")
 
     out = {
