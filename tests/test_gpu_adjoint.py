@@ -95,6 +95,19 @@ def _rhs_vjp_vs_autograd(c):
 def test_step_vjp_matches_reference_autograd(nd, n, nf, bc):
     _say("step_vjp", nd, n, nf, bc)
     c = W.random_case(nd, n, nf=nf, seed=50 + nd, bc=bc, speed=150.0)
+    _step_vjp_vs_autograd(c)
+
+
+@pytest.mark.parametrize("nd,n,nf,bc", [CASES[2], CASES[5]])
+def test_hll_step_vjp_matches_reference_autograd(nd, n, nf, bc):
+    """The step adjoint through HLL faces (reading 16)."""
+    _say("hll step_vjp", nd, n, nf, bc)
+    c = W.random_case(nd, n, nf=nf, seed=55 + nd, bc=bc, speed=150.0)
+    c.riemann = 1
+    _step_vjp_vs_autograd(c)
+
+
+def _step_vjp_vs_autograd(c):
     O = oracle.Oracle(c)
     q = O.prim_to_cons(c.w)
     dt = 0.4 / O.max_signal(q)
