@@ -52,6 +52,7 @@ class OrcProblem(ctypes.Structure):
         ("weno_eps", ctypes.c_double),
         ("weno_variant", ctypes.c_int32),
         ("riemann", ctypes.c_int32),
+        ("low_mach", ctypes.c_int32),
     ]
 
 
@@ -81,6 +82,7 @@ def lib():
             "orc_teno5_right": (ctypes.c_double, [dp, ctypes.c_double, ctypes.c_double]),
             "orc_hllc": (ctypes.c_int, [P, ctypes.c_int, dp, dp, dp, dp]),
             "orc_hll": (ctypes.c_int, [P, ctypes.c_int, dp, dp, dp, dp]),
+            "orc_thornber": (None, [P, ctypes.c_int, dp, dp]),
             "orc_rhs": (ctypes.c_int, [P, dp, dp]),
             "orc_rhs_cells": (ctypes.c_int, [P, dp, ctypes.c_int64, i64p, dp]),
             "orc_max_signal": (ctypes.c_int, [P, dp, dp]),
@@ -102,7 +104,7 @@ def lib():
 
 
 def problem(ndim, n, num_fluids, dx, gamma, pi_inf, bc_lo, bc_hi, weno_eps=1e-6, weno_variant=0,
-            riemann=0) -> OrcProblem:
+            riemann=0, low_mach=0) -> OrcProblem:
     P = OrcProblem()
     P.ndim = ndim
     n = tuple(n) + (1,) * (3 - len(n))
@@ -118,6 +120,7 @@ def problem(ndim, n, num_fluids, dx, gamma, pi_inf, bc_lo, bc_hi, weno_eps=1e-6,
     P.weno_eps = weno_eps
     P.weno_variant = int(weno_variant)
     P.riemann = int(riemann)
+    P.low_mach = int(low_mach)
     return P
 
 
@@ -233,6 +236,13 @@ class Oracle:
         uf = ctypes.c_double()
         rc = self.L.orc_hllc(ctypes.byref(self.P), d, _dp(wl), _dp(wr), _dp(F), ctypes.byref(uf))
         return F, uf.value, rc
+
+    def thornber(self, d, wl, wr):
+        """The low-Mach corrected face states (copies)."""
+        wl = np.array(wl, dtype=np.float64)
+        wr = np.array(wr, dtype=np.float64)
+        self.L.orc_thornber(ctypes.byref(self.P), d, _dp(wl), _dp(wr))
+        return wl, wr
 
     def hll(self, d, wl, wr):
         """HLL face flux and face velocity (Sec. 3.2.2)."""

@@ -50,6 +50,7 @@ typedef struct {
   double weno_eps;
   int32_t weno_variant; /* 0: WENO5-JS (Sec. 3.2.1), 1: WENO5-Z, 2: TENO5 (Sec. 4.2.2), 3: WENO5-M (Sec. 3.2.1) */
   int32_t riemann;      /* 0: HLLC, 1: HLL (Sec. 3.2.2) */
+  int32_t low_mach;     /* 0: none, 1: the Thornber et al. velocity correction (Sec. 4.2, low-Mach treatment) */
 } orc_problem;
 
 /* ------------------------------------------------------------------------ */
@@ -86,6 +87,7 @@ int orc_validate(const orc_problem* P) {
   if (!(P->weno_eps > 0)) return ORC_ERR_ARG;
   if (P->weno_variant < 0 || P->weno_variant > 3) return ORC_ERR_ARG;
   if (P->riemann < 0 || P->riemann > 1) return ORC_ERR_ARG;
+  if (P->low_mach < 0 || P->low_mach > 1) return ORC_ERR_ARG;
   return ORC_OK;
 }
 
@@ -478,6 +480,26 @@ int orc_hll(const orc_problem* P, int d, const double* WL, const double* WR, dou
 }
 
 /* ------------------------------------------------------------------------ */
+/* Low-Mach correction of Thornber et al., as the paper prints it (Sec. 4.2,*/
+/* low-Mach treatment): with z = min(max(|u_L|/c_L, |u_R|/c_R), 1) the face-*/
+/* normal velocities of the two reconstructed states become                 */
+/*   u_L* = (u_L + u_R)/2 + z (u_L - u_R)/2,  u_R* = (u_L + u_R)/2 + z (u_R - u_L)/2,*/
+/* and replace u_L, u_R in the face solver (wave speeds and fluxes).        */
+/* Reading: c_L, c_R are the sound speeds of the uncorrected states.        */
+/* ------------------------------------------------------------------------ */
+void orc_thornber(const orc_problem* P, int d, double* WL, double* WR) {
+  face_state L, R;
+  face_side(P, d, WL, &L);
+  face_side(P, d, WR, &R);
+  double mL = fabs(L.un) / L.c, mR = fabs(R.un) / R.c;
+  double z = (mL >= mR) ? mL : mR;
+  if (z > 1.0) z = 1.0;
+  double uL = WL[row_mom(P, d)], uR = WR[row_mom(P, d)];
+  WL[row_mom(P, d)] = 0.5 * (uL + uR) + z * (0.5 * (uL - uR));
+  WR[row_mom(P, d)] = 0.5 * (uL + uR) + z * (0.5 * (uR - uL));
+}
+
+/* ------------------------------------------------------------------------ */
 /* Face flux along axis d at the face on the low side of cell idx (face     */
 /* m - 1/2 with m = idx[d]): cells m-3..m+2 are loaded (ghost layers mapped),*/
 /* converted to primitive variables, reconstructed component-wise (left     */
@@ -515,6 +537,7 @@ static int face_flux(const orc_problem* P, const double* q, int d, const int idx
       WR[v] = orc_weno5_js_right(fr, P->weno_eps);
     }
   }
+  if (P->low_mach == 1) orc_thornber(P, d, WL, WR);
   return P->riemann == 1 ? orc_hll(P, d, WL, WR, F, uf) : orc_hllc(P, d, WL, WR, F, uf);
 }
 

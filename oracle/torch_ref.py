@@ -42,7 +42,7 @@ def sqrt(x):
 
 class Problem:
     def __init__(self, ndim, n, num_fluids, dx, gamma, pi_inf, bc_lo, bc_hi, weno_eps=1e-6, weno_variant=0,
-                 riemann=0):
+                 riemann=0, low_mach=0):
         self.ndim = ndim
         self.n = tuple(n) + (1,) * (3 - len(n))
         self.nf = num_fluids
@@ -54,6 +54,7 @@ class Problem:
         self.eps = weno_eps
         self.weno_variant = int(weno_variant)
         self.riemann = int(riemann)
+        self.low_mach = int(low_mach)
         self.neq = self.nf + ndim + 1 + (2 if self.nf == 2 else 0)
         self.G = [1.0 / (g - 1.0) for g in self.gamma]
         self.P = [g * p / (g - 1.0) for g, p in zip(self.gamma, self.pi_inf)]
@@ -300,6 +301,24 @@ def hllc(P: Problem, d, WL, WR):
     return torch.stack(F), uf, (L["c2"], R["c2"])
 
 
+def thornber(P: Problem, d, WL, WR):
+    """Thornber et al. low-Mach correction of the face-normal velocities (the
+    form printed in the paper's low-Mach section), sound speeds of the
+    uncorrected states."""
+    L, R = _face_side(P, d, WL), _face_side(P, d, WR)
+    mL = torch.abs(L["un"]) / L["c"]
+    mR = torch.abs(R["un"]) / R["c"]
+    z = torch.where(mL >= mR, mL, mR)
+    z = torch.where(z > 1.0, torch.ones_like(z), z)
+    r = P.row_mom(d)
+    uL, uR = WL[r], WR[r]
+    uLs = 0.5 * (uL + uR) + z * (0.5 * (uL - uR))
+    uRs = 0.5 * (uL + uR) + z * (0.5 * (uR - uL))
+    WL = torch.cat([WL[:r], uLs.unsqueeze(0), WL[r + 1:]], dim=0)
+    WR = torch.cat([WR[:r], uRs.unsqueeze(0), WR[r + 1:]], dim=0)
+    return WL, WR
+
+
 def hll(P: Problem, d, WL, WR):
     """HLL flux (Sec. 3.2.2): two waves, one averaged state; the volume
     fractions take the same formula on alpha u_n and the face velocity is the
@@ -338,6 +357,8 @@ def axis_contribution(P: Problem, q, d):
     weno = {0: weno5_js_left, 1: weno5_z_left, 2: teno5_left, 3: weno5_m_left}[P.weno_variant]
     WL = weno(fl[0], fl[1], fl[2], fl[3], fl[4], P.eps)
     WR = weno(fr[4], fr[3], fr[2], fr[1], fr[0], P.eps)
+    if P.low_mach == 1:
+        WL, WR = thornber(P, d, WL, WR)
     F, uf, _ = (hll if P.riemann == 1 else hllc)(P, d, WL, WR)
     inv_dx = 1.0 / P.dx[d]
     Flo, Fhi = _sl(F, ax, 0, n), _sl(F, ax, 1, n)

@@ -57,6 +57,7 @@ class Case:
     weno_eps: float = 1e-6
     weno_variant: int = 0   # 0: WENO5-JS, 1: WENO5-Z, 2: TENO5, 3: WENO5-M
     riemann: int = 0        # 0: HLLC, 1: HLL
+    low_mach: int = 0       # 0: none, 1: Thornber et al. velocity correction
     extra: dict = field(default_factory=dict)
 
     @property
@@ -73,7 +74,7 @@ class Case:
                     dx=tuple(self.dx), gamma=tuple(self.gamma),
                     pi_inf=tuple(self.pi_inf), bc_lo=tuple(self.bc_lo),
                     bc_hi=tuple(self.bc_hi), weno_eps=self.weno_eps, weno_variant=self.weno_variant,
-                    riemann=self.riemann)
+                    riemann=self.riemann, low_mach=self.low_mach)
 
 
 def _pad3(t, fill):
@@ -466,3 +467,28 @@ CONFIGS = {
     "C3": "adjoint on the shock-cylinder physics at 256x256, 200 steps",
     "C4": "3D periodic slab, 512^3, 100 steps, FP32 form vs FP64",
 }
+
+
+def gresho(n: int = 32, mach: float = 0.01, gamma: float = 1.4) -> Case:
+    """Gresho vortex (the paper's low-Mach validation case): a stationary
+    vortex of the incompressible Euler equations, u_theta = 5r (r < 0.2),
+    2 - 5r (0.2 <= r < 0.4), 0 outside, with the pressure that balances it;
+    rho = 1, ideal gas, background pressure p0 = 1/(gamma M^2) so that the
+    peak speed 1 has Mach M.  Periodic unit square, n x n cells."""
+    dx = 1.0 / n
+    x = _centres(n, dx)
+    X, Y = np.meshgrid(x, x, indexing="xy")
+    dxc, dyc = X - 0.5, Y - 0.5
+    r = np.hypot(dxc, dyc)
+    ut = np.where(r < 0.2, 5.0 * r, np.where(r < 0.4, 2.0 - 5.0 * r, 0.0))
+    p0 = 1.0 / (gamma * mach * mach)
+    with np.errstate(divide="ignore"):
+        p = np.where(r < 0.2, p0 + 12.5 * r * r,
+                     np.where(r < 0.4, p0 + 12.5 * r * r + 4.0 - 20.0 * r + 4.0 * np.log(np.maximum(5.0 * r, 1e-300)),
+                              p0 - 2.0 + 4.0 * np.log(2.0)))
+    rs = np.where(r > 0, r, 1.0)
+    u = -ut * dyc / rs
+    v = ut * dxc / rs
+    w = np.stack([np.ones_like(X), u, v, p]).reshape(4, 1, n, n)
+    return Case("gresho", 2, (n, n, 1), 1, (dx, dx, 1.0), (gamma, gamma), (0.0, 0.0),
+                (PERIODIC,) * 3, (PERIODIC,) * 3, w)
