@@ -264,14 +264,14 @@ def paper_shape_grind(steps=20, warmup=3):
     return out
 
 
-def variant_grind(case, variant, steps=20, warmup=3, riemann=0):
+def variant_grind(case, variant, steps=20, warmup=3, riemann=0, low_mach=0):
     """The same bubble cloud with the WENO5-Z (1) or TENO5 (2) weights of
     Sec. 4.2.2, the mapped WENO5-M weights (3) of Sec. 3.2.1, or (riemann=1)
     the HLL face solver of Sec. 3.2.2: FP64 and FP32 grind."""
     import dataclasses
 
     from paper_2503_07953_amd.solver import Solver
-    cz = dataclasses.replace(case, weno_variant=variant, riemann=riemann)
+    cz = dataclasses.replace(case, weno_variant=variant, riemann=riemann, low_mach=low_mach)
     out = {}
     for prec in ("fp64", "fp32"):
         S = Solver.from_case(cz, precision=prec)
@@ -390,6 +390,7 @@ def main():
                  "bubble_cloud_teno5": variant_grind(case, 2, args.steps, args.warmup),
                  "bubble_cloud_weno_m": variant_grind(case, 3, args.steps, args.warmup),
                  "bubble_cloud_hll": variant_grind(case, 0, args.steps, args.warmup, riemann=1),
+                 "bubble_cloud_low_mach": variant_grind(case, 0, args.steps, args.warmup, low_mach=1),
                  "paper_benchmark_shape": paper_shape_grind(args.steps, args.warmup)}
         log(f"extra: {extra}")
     slab = None

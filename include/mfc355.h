@@ -46,7 +46,7 @@
 extern "C" {
 #endif
 
-#define MFC_ABI_VERSION 3
+#define MFC_ABI_VERSION 4
 
 enum {
   MFC_OK = 0,
@@ -95,6 +95,16 @@ enum { MFC_WENO_JS = 0, MFC_WENO_Z = 1, MFC_TENO = 2, MFC_WENO_M = 3 };
  *             (the paper prints no HLL formula: these are the readings). */
 enum { MFC_HLLC = 0, MFC_HLL = 1 };
 
+/* Low-Mach treatment (the paper's low-Mach section):
+ *   MFC_LOW_MACH_NONE      the face states as reconstructed;
+ *   MFC_LOW_MACH_THORNBER  Thornber et al.: with z = min(max(|u_L|/c_L,
+ *                          |u_R|/c_R), 1) the face-normal velocities become
+ *                          (u_L + u_R)/2 +- z (u_L - u_R)/2 before the face
+ *                          solver (either one); c of the uncorrected states.
+ *                          The adjoint entry points return
+ *                          MFC_ERR_UNSUPPORTED with it. */
+enum { MFC_LOW_MACH_NONE = 0, MFC_LOW_MACH_THORNBER = 1 };
+
 typedef struct {
   int32_t abi_version; /* must equal MFC_ABI_VERSION */
   int32_t ndim;        /* 1, 2 or 3 */
@@ -110,6 +120,7 @@ typedef struct {
   double weno_eps;     /* WENO smoothness regularization, > 0 (1e-6) */
   int32_t weno_variant; /* MFC_WENO_JS, MFC_WENO_Z, MFC_TENO or MFC_WENO_M */
   int32_t riemann_solver; /* MFC_HLLC (0) or MFC_HLL */
+  int32_t low_mach;       /* MFC_LOW_MACH_NONE (0) or MFC_LOW_MACH_THORNBER */
 } mfc_problem;
 
 typedef struct mfc_ctx mfc_ctx;
@@ -171,7 +182,8 @@ int mfc_conserved_sums(mfc_ctx* ctx, const void* q, double* sums_dev, void* hip_
  * 8 GiB threshold.
  * Outputs may not alias inputs.  accumulate != 0 adds to the output instead of
  * overwriting it.  Both face solvers (HLLC, HLL) have their hand-written
- * adjoint. */
+ * adjoint; contexts with low_mach != MFC_LOW_MACH_NONE get
+ * MFC_ERR_UNSUPPORTED from mfc_rhs_vjp, mfc_step_vjp and mfc_step_vjp_stages. */
 
 /* q_bar (+)= (dL/dq)^T rhs_bar, L the right-hand side of mfc_rhs at q. */
 int mfc_rhs_vjp(mfc_ctx* ctx, const void* q, const void* rhs_bar, void* q_bar, int accumulate,

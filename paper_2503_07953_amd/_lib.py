@@ -13,9 +13,10 @@ import os
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libmfc355.so")
 
-MFC_ABI_VERSION = 3
+MFC_ABI_VERSION = 4
 MFC_WENO_JS, MFC_WENO_Z, MFC_TENO, MFC_WENO_M = 0, 1, 2, 3
 MFC_HLLC, MFC_HLL = 0, 1
+MFC_LOW_MACH_NONE, MFC_LOW_MACH_THORNBER = 0, 1
 MFC_OK, MFC_ERR_ARG, MFC_ERR_SHAPE, MFC_ERR_UNSUPPORTED = 0, -1, -2, -3
 MFC_ERR_HIP, MFC_ERR_NONFINITE, MFC_ERR_ALLOC = -4, -5, -6
 MFC_BC_PERIODIC, MFC_BC_EXTRAP, MFC_BC_SLIPWALL = 0, 1, 2
@@ -37,6 +38,7 @@ class mfc_problem(ctypes.Structure):
         ("weno_eps", ctypes.c_double),
         ("weno_variant", ctypes.c_int32),
         ("riemann_solver", ctypes.c_int32),
+        ("low_mach", ctypes.c_int32),
     ]
 
 
@@ -116,7 +118,8 @@ class MfcError(RuntimeError):
 
 
 def make_problem(ndim, n, num_fluids, dx, gamma, pi_inf, bc_lo, bc_hi, weno_eps=1e-6,
-                 precision=MFC_FP64, weno_variant=MFC_WENO_JS, riemann=MFC_HLLC) -> mfc_problem:
+                 precision=MFC_FP64, weno_variant=MFC_WENO_JS, riemann=MFC_HLLC,
+                 low_mach=MFC_LOW_MACH_NONE) -> mfc_problem:
     p = mfc_problem()
     p.abi_version = MFC_ABI_VERSION
     p.ndim = int(ndim)
@@ -134,4 +137,5 @@ def make_problem(ndim, n, num_fluids, dx, gamma, pi_inf, bc_lo, bc_hi, weno_eps=
     p.weno_eps = float(weno_eps)
     p.weno_variant = int(weno_variant)
     p.riemann_solver = int(riemann)
+    p.low_mach = int(low_mach)
     return p

@@ -202,6 +202,7 @@ mfc::Params make_params(const mfc_problem& p) {
   pm.eps = p.weno_eps;
   pm.weno_variant = p.weno_variant;
   pm.riemann = p.riemann_solver;
+  pm.low_mach = p.low_mach;
   pm.ncell = (long long)p.n[0] * p.n[1] * p.n[2];
   return pm;
 }
@@ -261,6 +262,7 @@ int mfc_validate(const mfc_problem* p) {
   if (!(p->weno_eps > 0.0)) return MFC_ERR_ARG;
   if (p->weno_variant < MFC_WENO_JS || p->weno_variant > MFC_WENO_M) return MFC_ERR_UNSUPPORTED;
   if (p->riemann_solver != MFC_HLLC && p->riemann_solver != MFC_HLL) return MFC_ERR_UNSUPPORTED;
+  if (p->low_mach != MFC_LOW_MACH_NONE && p->low_mach != MFC_LOW_MACH_THORNBER) return MFC_ERR_UNSUPPORTED;
   return MFC_OK;
 }
 
@@ -490,6 +492,7 @@ int mfc_rhs_vjp(mfc_ctx* c, const void* q, const void* rhs_bar, void* q_bar, int
   if (!c) return MFC_ERR_ARG;
   if (int rd = check_device(c)) return rd;
   if (c->prob.precision != MFC_FP64) return fail(c, MFC_ERR_UNSUPPORTED, "adjoint entry points are FP64 only");
+  if (c->prob.low_mach != MFC_LOW_MACH_NONE) return fail(c, MFC_ERR_UNSUPPORTED, "no adjoint of the low-Mach correction");
   int r;
   if ((r = check_array(c, q, "q")) || (r = check_array(c, rhs_bar, "rhs_bar")) || (r = check_array(c, q_bar, "q_bar")))
     return r;
@@ -505,6 +508,7 @@ int mfc_step_vjp(mfc_ctx* c, const void* q_n, double dt, const void* qnp1_bar, v
   if (!c) return MFC_ERR_ARG;
   if (int rd = check_device(c)) return rd;
   if (c->prob.precision != MFC_FP64) return fail(c, MFC_ERR_UNSUPPORTED, "adjoint entry points are FP64 only");
+  if (c->prob.low_mach != MFC_LOW_MACH_NONE) return fail(c, MFC_ERR_UNSUPPORTED, "no adjoint of the low-Mach correction");
   int r;
   if ((r = check_array(c, q_n, "q_n")) || (r = check_array(c, qnp1_bar, "qnp1_bar")) ||
       (r = check_array(c, qn_bar, "qn_bar")))
@@ -556,6 +560,7 @@ int mfc_step_vjp_stages(mfc_ctx* c, const void* q_n, const void* q1, const void*
   if (!c) return MFC_ERR_ARG;
   if (int rd = check_device(c)) return rd;
   if (c->prob.precision != MFC_FP64) return fail(c, MFC_ERR_UNSUPPORTED, "adjoint entry points are FP64 only");
+  if (c->prob.low_mach != MFC_LOW_MACH_NONE) return fail(c, MFC_ERR_UNSUPPORTED, "no adjoint of the low-Mach correction");
   int r;
   if ((r = check_array(c, q_n, "q_n")) || (r = check_array(c, q1, "q1")) || (r = check_array(c, q2, "q2")) ||
       (r = check_array(c, qnp1_bar, "qnp1_bar")) || (r = check_array(c, qn_bar, "qn_bar")))

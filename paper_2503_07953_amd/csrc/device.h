@@ -21,6 +21,7 @@ struct Params {
   int bc_hi[3];        // BC kind per axis, high side
   int weno_variant;    // 0: WENO5-JS, 1: WENO5-Z, 2: TENO5, 3: WENO5-M
   int riemann;         // 0: HLLC, 1: HLL (Sec. 3.2.2)
+  int low_mach;        // 0: none, 1: Thornber et al. velocity correction
   double inv_dx[3];    // 1/dx per axis
   double G[2];         // 1/(gamma_i - 1)
   double P[2];         // gamma_i pi_inf,i/(gamma_i - 1)
@@ -638,6 +639,37 @@ __host__ __device__ __forceinline__ bool hll(const Params& pm, const T* WL, cons
 #pragma unroll
   for (int v = 0; v < R::NEQ; ++v) finite = finite && __builtin_isfinite(F[v]);
   return !(c2L > 0.0 && c2R > 0.0 && finite);
+}
+
+// Low-Mach correction of Thornber et al. (the paper's low-Mach section): with
+// z = min(max(|u_L|/c_L, |u_R|/c_R), 1), sound speeds of the states as
+// reconstructed, the face-normal velocities become
+//   u_L* = (u_L + u_R)/2 + z (u_L - u_R)/2,  u_R* = (u_L + u_R)/2 + z (u_R - u_L)/2
+// and replace u_L, u_R in the face solver.  The Mach numbers and z in double.
+template <int NF, int D, int DIR, typename T>
+__host__ __device__ __forceinline__ void thornber(const Params& pm, T* WL, T* WR) {
+  using R = Rows<NF, D>;
+  double rhoL = double(WL[0]), rhoR = double(WR[0]);
+  if constexpr (NF == 2) {
+    rhoL = double(WL[0]) + double(WL[1]);
+    rhoR = double(WR[0]) + double(WR[1]);
+  }
+  double GamL, PiL, GamR, PiR;
+  if constexpr (NF == 2) {
+    mixture<NF, double>(pm, double(WL[R::ALPHA]), double(WL[R::ALPHA + 1]), GamL, PiL);
+    mixture<NF, double>(pm, double(WR[R::ALPHA]), double(WR[R::ALPHA + 1]), GamR, PiR);
+  } else {
+    mixture<NF, double>(pm, 1.0, 0.0, GamL, PiL);
+    mixture<NF, double>(pm, 1.0, 0.0, GamR, PiR);
+  }
+  const double uL = double(WL[R::MOM + DIR]), uR = double(WR[R::MOM + DIR]);
+  const double cL = sqrt(sound_speed_sq(rhoL, double(WL[R::E]), GamL, PiL));
+  const double cR = sqrt(sound_speed_sq(rhoR, double(WR[R::E]), GamR, PiR));
+  const double mL = fabs(uL) / cL, mR = fabs(uR) / cR;
+  double z = (mL >= mR) ? mL : mR;
+  if (z > 1.0) z = 1.0;
+  WL[R::MOM + DIR] = T(0.5 * (uL + uR) + z * (0.5 * (uL - uR)));
+  WR[R::MOM + DIR] = T(0.5 * (uL + uR) + z * (0.5 * (uR - uL)));
 }
 
 // The face solver of a kernel instantiation: RS = 0 HLLC, 1 HLL.

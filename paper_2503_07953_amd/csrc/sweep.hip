@@ -255,7 +255,10 @@ __global__ __launch_bounds__((Tile<DIR, D, Real>::NT)) void sweep_kernel(Params 
     Real WL[NEQ];
 #pragma unroll
     for (int v = 0; v < NEQ; ++v) WL[v] = sh[lds_index<DIR, D, Real>(v, a - 1, b)];
-    const bool bad = riemann<RS, NF, D, DIR, Real>(pm, WL, WRc, F, uf);
+    // RS: face solver (bit 0: HLL) and low-Mach correction (bit 1), both
+    // compile-time so that neither costs registers where it is off
+    if constexpr ((RS & 2) != 0) thornber<NF, D, DIR, Real>(pm, WL, WRc);
+    const bool bad = riemann<RS & 1, NF, D, DIR, Real>(pm, WL, WRc, F, uf);
     if (bad) atomicOr(flag, 1);
   }
   __syncthreads();
@@ -414,13 +417,17 @@ static hipError_t launch_rhs_t(const Params& pm, const Real* qk, Real* acc, cons
   return e;
 }
 
-// The face solver is a compile-time choice too (a run-time branch would make
-// every kernel hold the registers of both).
+// The face solver and the low-Mach correction are compile-time choices too (a
+// run-time branch cost the double x pass 6 VGPRs and a wave per SIMD).
 template <int NF, int D, typename Real, int WV>
 static hipError_t by_riemann(const Params& pm, const Real* qk, Real* acc, const Real* qn, Real* qout, StageArgs st,
                              bool final_step, int* flag, hipStream_t s, PassTimer* tm, const SignalFuse* sig) {
-  if (pm.riemann == 1) return launch_rhs_t<NF, D, Real, WV, 1>(pm, qk, acc, qn, qout, st, final_step, flag, s, tm, sig);
-  return launch_rhs_t<NF, D, Real, WV, 0>(pm, qk, acc, qn, qout, st, final_step, flag, s, tm, sig);
+  switch (pm.riemann + 2 * pm.low_mach) {
+    case 1: return launch_rhs_t<NF, D, Real, WV, 1>(pm, qk, acc, qn, qout, st, final_step, flag, s, tm, sig);
+    case 2: return launch_rhs_t<NF, D, Real, WV, 2>(pm, qk, acc, qn, qout, st, final_step, flag, s, tm, sig);
+    case 3: return launch_rhs_t<NF, D, Real, WV, 3>(pm, qk, acc, qn, qout, st, final_step, flag, s, tm, sig);
+    default: return launch_rhs_t<NF, D, Real, WV, 0>(pm, qk, acc, qn, qout, st, final_step, flag, s, tm, sig);
+  }
 }
 
 template <typename Real>

@@ -24,12 +24,12 @@ class Solver:
     """Owns one mfc_ctx.  `precision` is "fp64" or "fp32" (the mixed FP32 form)."""
 
     def __init__(self, ndim, n, num_fluids, dx, gamma, pi_inf, bc_lo, bc_hi, weno_eps=1e-6,
-                 precision="fp64", device="cuda", weno_variant=0, riemann=0):
+                 precision="fp64", device="cuda", weno_variant=0, riemann=0, low_mach=0):
         self.lib = L.load()
         self.precision = precision
         prec = L.MFC_FP64 if precision == "fp64" else L.MFC_FP32_MIXED
         self.prob = L.make_problem(ndim, n, num_fluids, dx, gamma, pi_inf, bc_lo, bc_hi, weno_eps, prec, weno_variant,
-                                   riemann)
+                                   riemann, low_mach)
         self.dtype = torch.float64 if precision == "fp64" else torch.float32
         self.device = torch.device(device)
         rc = self.lib.mfc_validate(ctypes.byref(self.prob))

@@ -74,6 +74,8 @@ def test_num_eqs(L):
     (dict(riemann=1), 0),
     (dict(riemann=2), -3),
     (dict(riemann=-1), -3),
+    (dict(low_mach=1), 0),
+    (dict(low_mach=2), -3),
 ])
 def test_validation_codes(L, kw, code):
     lib = L.load()
