@@ -100,9 +100,7 @@ enum { MFC_HLLC = 0, MFC_HLL = 1 };
  *   MFC_LOW_MACH_THORNBER  Thornber et al.: with z = min(max(|u_L|/c_L,
  *                          |u_R|/c_R), 1) the face-normal velocities become
  *                          (u_L + u_R)/2 +- z (u_L - u_R)/2 before the face
- *                          solver (either one); c of the uncorrected states.
- *                          The adjoint entry points return
- *                          MFC_ERR_UNSUPPORTED with it. */
+ *                          solver (either one); c of the uncorrected states. */
 enum { MFC_LOW_MACH_NONE = 0, MFC_LOW_MACH_THORNBER = 1 };
 
 typedef struct {
@@ -181,9 +179,8 @@ int mfc_conserved_sums(mfc_ctx* ctx, const void* q, double* sums_dev, void* hip_
  * MFC355_ADJOINT_FACE_BUDGET (bytes, read at that first call) overrides the
  * 8 GiB threshold.
  * Outputs may not alias inputs.  accumulate != 0 adds to the output instead of
- * overwriting it.  Both face solvers (HLLC, HLL) have their hand-written
- * adjoint; contexts with low_mach != MFC_LOW_MACH_NONE get
- * MFC_ERR_UNSUPPORTED from mfc_rhs_vjp, mfc_step_vjp and mfc_step_vjp_stages. */
+ * overwriting it.  Both face solvers (HLLC, HLL) and the low-Mach correction
+ * have their hand-written adjoint. */
 
 /* q_bar (+)= (dL/dq)^T rhs_bar, L the right-hand side of mfc_rhs at q. */
 int mfc_rhs_vjp(mfc_ctx* ctx, const void* q, const void* rhs_bar, void* q_bar, int accumulate,

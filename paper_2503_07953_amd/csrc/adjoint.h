@@ -715,6 +715,43 @@ __host__ __device__ __forceinline__ void hll_vjp(const Params& pm, const double*
   side_scalars_vjp<NF, D, DIR>(pm, WR, Rs, rhoRb, 0.0, 0.0, pRb, unRb, ERb, cRb, WRb);
 }
 
+// Adjoint of the low-Mach correction (thornber() in device.h).  Given the
+// cotangents WLb, WRb of the corrected states (which differ from the states
+// as reconstructed only in the normal velocity, so their sound speeds are
+// those of the originals) and the original normal velocities uL, uR, turn
+// WLb, WRb into the cotangents of the states as reconstructed:
+//   uL* = (1 + z)/2 uL + (1 - z)/2 uR,  uR* = (1 - z)/2 uL + (1 + z)/2 uR,
+//   zbar = (uL - uR)/2 (uL*bar - uR*bar), none when z is clipped at 1, to the
+//   Mach number the max took (ties: first), and M = |u|/c gives u sign(u)/c and
+//   c -|u|/c^2, pushed through the side-scalar adjoint.
+template <int NF, int D, int DIR>
+__host__ __device__ __forceinline__ void thornber_vjp(const Params& pm, const double* WL, const double* WR,
+                                                      double uL, double uR, double* WLb, double* WRb) {
+  using R = Rows<NF, D>;
+  SideState<NF, D> L, Rs;
+  side_state<NF, D, DIR>(pm, WL, L);
+  side_state<NF, D, DIR>(pm, WR, Rs);
+  const double mL = fabs(uL) / L.c, mR = fabs(uR) / Rs.c;
+  const bool left = mL >= mR;
+  const double zm = left ? mL : mR;
+  const bool clipped = zm > 1.0;
+  const double z = clipped ? 1.0 : zm;
+  const double gl = WLb[R::MOM + DIR], gr = WRb[R::MOM + DIR];
+  WLb[R::MOM + DIR] = 0.5 * (1.0 + z) * gl + 0.5 * (1.0 - z) * gr;
+  WRb[R::MOM + DIR] = 0.5 * (1.0 - z) * gl + 0.5 * (1.0 + z) * gr;
+  if (clipped) return;
+  const double zb = 0.5 * (uL - uR) * (gl - gr);
+  if (left) {
+    const double rc = 1.0 / L.c;
+    WLb[R::MOM + DIR] += zb * ((uL > 0.0) ? rc : ((uL < 0.0) ? -rc : 0.0));
+    side_scalars_vjp<NF, D, DIR>(pm, WL, L, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, -zb * fabs(uL) * rc * rc, WLb);
+  } else {
+    const double rc = 1.0 / Rs.c;
+    WRb[R::MOM + DIR] += zb * ((uR > 0.0) ? rc : ((uR < 0.0) ? -rc : 0.0));
+    side_scalars_vjp<NF, D, DIR>(pm, WR, Rs, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, -zb * fabs(uR) * rc * rc, WRb);
+  }
+}
+
 // The face-solver adjoint of a kernel instantiation: RS = 0 HLLC, 1 HLL.
 template <int RS, int NF, int D, int DIR>
 __host__ __device__ __forceinline__ void riemann_vjp(const Params& pm, const double* WL, const double* WR,

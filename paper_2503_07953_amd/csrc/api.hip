@@ -492,7 +492,6 @@ int mfc_rhs_vjp(mfc_ctx* c, const void* q, const void* rhs_bar, void* q_bar, int
   if (!c) return MFC_ERR_ARG;
   if (int rd = check_device(c)) return rd;
   if (c->prob.precision != MFC_FP64) return fail(c, MFC_ERR_UNSUPPORTED, "adjoint entry points are FP64 only");
-  if (c->prob.low_mach != MFC_LOW_MACH_NONE) return fail(c, MFC_ERR_UNSUPPORTED, "no adjoint of the low-Mach correction");
   int r;
   if ((r = check_array(c, q, "q")) || (r = check_array(c, rhs_bar, "rhs_bar")) || (r = check_array(c, q_bar, "q_bar")))
     return r;
@@ -508,7 +507,6 @@ int mfc_step_vjp(mfc_ctx* c, const void* q_n, double dt, const void* qnp1_bar, v
   if (!c) return MFC_ERR_ARG;
   if (int rd = check_device(c)) return rd;
   if (c->prob.precision != MFC_FP64) return fail(c, MFC_ERR_UNSUPPORTED, "adjoint entry points are FP64 only");
-  if (c->prob.low_mach != MFC_LOW_MACH_NONE) return fail(c, MFC_ERR_UNSUPPORTED, "no adjoint of the low-Mach correction");
   int r;
   if ((r = check_array(c, q_n, "q_n")) || (r = check_array(c, qnp1_bar, "qnp1_bar")) ||
       (r = check_array(c, qn_bar, "qn_bar")))
@@ -560,7 +558,6 @@ int mfc_step_vjp_stages(mfc_ctx* c, const void* q_n, const void* q1, const void*
   if (!c) return MFC_ERR_ARG;
   if (int rd = check_device(c)) return rd;
   if (c->prob.precision != MFC_FP64) return fail(c, MFC_ERR_UNSUPPORTED, "adjoint entry points are FP64 only");
-  if (c->prob.low_mach != MFC_LOW_MACH_NONE) return fail(c, MFC_ERR_UNSUPPORTED, "no adjoint of the low-Mach correction");
   int r;
   if ((r = check_array(c, q_n, "q_n")) || (r = check_array(c, q1, "q1")) || (r = check_array(c, q2, "q2")) ||
       (r = check_array(c, qnp1_bar, "qnp1_bar")) || (r = check_array(c, qn_bar, "qn_bar")))

@@ -198,7 +198,16 @@ __device__ __forceinline__ void face_tile(const Params pm, const double* __restr
 #pragma unroll
   for (int v = 0; v < NEQ; ++v) WLb[v] = WRb[v] = 0.0;
   double uf;
-  riemann_vjp<RS, NF, D, DIR>(pm, WL, WR, Fb, ufb, WLb, WRb, &uf);
+  // RS bit 1: the low-Mach correction precedes the face solver; its adjoint
+  // follows the solver's
+  double uL0 = 0.0, uR0 = 0.0;
+  if constexpr ((RS & 2) != 0) {
+    uL0 = WL[Rows<NF, D>::MOM + DIR];
+    uR0 = WR[Rows<NF, D>::MOM + DIR];
+    thornber<NF, D, DIR, double>(pm, WL, WR);
+  }
+  riemann_vjp<RS & 1, NF, D, DIR>(pm, WL, WR, Fb, ufb, WLb, WRb, &uf);
+  if constexpr ((RS & 2) != 0) thornber_vjp<NF, D, DIR>(pm, WL, WR, uL0, uR0, WLb, WRb);
 
   const long long nfc = fg.count;
   // compiler-only memory barrier: the stencil values are read from LDS again
@@ -444,8 +453,12 @@ static hipError_t launch_rhs_vjp_t(const Params& pm, const double* q, const doub
 template <int NF, int D, int WV>
 static hipError_t vjp_by_riemann(const Params& pm, const double* q, const double* rbar, double* qbar,
                                  const VjpScratch& sc, bool accumulate, hipStream_t s, PassTimer* tm) {
-  if (pm.riemann == 1) return launch_rhs_vjp_t<NF, D, WV, 1>(pm, q, rbar, qbar, sc, accumulate, s, tm);
-  return launch_rhs_vjp_t<NF, D, WV, 0>(pm, q, rbar, qbar, sc, accumulate, s, tm);
+  switch (pm.riemann + 2 * pm.low_mach) {
+    case 1: return launch_rhs_vjp_t<NF, D, WV, 1>(pm, q, rbar, qbar, sc, accumulate, s, tm);
+    case 2: return launch_rhs_vjp_t<NF, D, WV, 2>(pm, q, rbar, qbar, sc, accumulate, s, tm);
+    case 3: return launch_rhs_vjp_t<NF, D, WV, 3>(pm, q, rbar, qbar, sc, accumulate, s, tm);
+    default: return launch_rhs_vjp_t<NF, D, WV, 0>(pm, q, rbar, qbar, sc, accumulate, s, tm);
+  }
 }
 
 hipError_t launch_rhs_vjp(int nf, int ndim, const Params& pm, const double* q, const double* rbar, double* qbar,

@@ -66,6 +66,16 @@ def test_hll_rhs_vjp_matches_reference_autograd(nd, n, nf, bc):
     _rhs_vjp_vs_autograd(c)
 
 
+@pytest.mark.parametrize("nd,n,nf,bc,riemann", [CASES[2] + (0,), CASES[5] + (0,), CASES[4] + (0,), CASES[2] + (1,)])
+def test_low_mach_rhs_vjp_matches_reference_autograd(nd, n, nf, bc, riemann):
+    """The adjoint through the low-Mach correction and the face solver."""
+    _say("low-mach rhs_vjp", nd, n, nf, bc, riemann)
+    c = W.random_case(nd, n, nf=nf, seed=75 + nd, bc=bc, speed=300.0 if nf == 1 else 150.0)
+    c.riemann = riemann
+    c.low_mach = 1
+    _rhs_vjp_vs_autograd(c)
+
+
 def _rhs_vjp_vs_autograd(c):
     nd, nf = c.ndim, c.num_fluids
     O = oracle.Oracle(c)
