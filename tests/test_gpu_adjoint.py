@@ -76,6 +76,19 @@ def test_low_mach_rhs_vjp_matches_reference_autograd(nd, n, nf, bc, riemann):
     _rhs_vjp_vs_autograd(c)
 
 
+@pytest.mark.parametrize("variant,riemann,low_mach,case", [
+    (1, 1, 1, 2), (3, 1, 1, 5), (2, 1, 1, 4), (3, 0, 1, 3), (1, 1, 0, 0)])
+def test_option_combinations_rhs_vjp_match_reference_autograd(variant, riemann, low_mach, case):
+    """The adjoint under crossed settings of the reconstruction weights, the
+    face solver and the low-Mach correction."""
+    nd, n, nf, bc = CASES[case]
+    _say("combination rhs_vjp", variant, riemann, low_mach, nd, n, nf, bc)
+    c = W.random_case(nd, n, nf=nf, seed=90 + 10 * variant + case, bc=bc,
+                      speed=300.0 if nf == 1 else 150.0)
+    c.weno_variant, c.riemann, c.low_mach = variant, riemann, low_mach
+    _rhs_vjp_vs_autograd(c)
+
+
 def _rhs_vjp_vs_autograd(c):
     nd, nf = c.ndim, c.num_fluids
     O = oracle.Oracle(c)

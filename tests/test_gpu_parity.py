@@ -269,6 +269,21 @@ def test_low_mach_correction_matches_oracle(name):
     _variant_steps_match(c, nf, nd, flux_scale=name.startswith("gresho"))
 
 
+@pytest.mark.parametrize("variant,riemann,low_mach,case", [
+    (1, 1, 1, 3), (3, 1, 1, 6), (3, 0, 1, 3), (2, 1, 0, 7),
+    (2, 1, 1, 0), (1, 0, 1, 7), (3, 1, 0, 5), (2, 0, 1, 4)])
+def test_option_combinations_match_oracle(variant, riemann, low_mach, case):
+    """The reconstruction weights (Sec. 4.2.2), the face solver (HLLC / HLL)
+    and the low-Mach correction are independent options, and every setting of
+    the three is a kernel of its own: crossed settings, RHS and 5 CFL steps."""
+    nd, n, nf, bc = CASES[case]
+    _say("combination", variant, riemann, low_mach, nd, n, nf, bc)
+    c = W.random_case(nd, n, nf=nf, seed=800 + 10 * variant + case, bc=bc,
+                      speed=400.0 if nf == 1 else 150.0)
+    c.weno_variant, c.riemann, c.low_mach = variant, riemann, low_mach
+    _variant_steps_match(c, nf, nd)
+
+
 def test_teno_rough_two_fluid_flagged_on_both_sides():
     """Two-fluid white noise under TENO5 reconstructs a face state with c^2 <= 0;
     the oracle refuses it and the library's check reports MFC_ERR_NONFINITE."""
