@@ -130,6 +130,17 @@ def test_hll_step_vjp_matches_reference_autograd(nd, n, nf, bc):
     _step_vjp_vs_autograd(c)
 
 
+@pytest.mark.parametrize("variant,riemann,low_mach,case", [(3, 1, 1, 2), (2, 0, 1, 4), (1, 1, 1, 5)])
+def test_option_combinations_step_vjp_match_reference_autograd(variant, riemann, low_mach, case):
+    """The SSP-RK3 step adjoint under crossed settings of the reconstruction
+    weights, the face solver and the low-Mach correction."""
+    nd, n, nf, bc = CASES[case]
+    _say("combination step_vjp", variant, riemann, low_mach, nd, n, nf, bc)
+    c = W.random_case(nd, n, nf=nf, seed=95 + 10 * variant + case, bc=bc, speed=150.0)
+    c.weno_variant, c.riemann, c.low_mach = variant, riemann, low_mach
+    _step_vjp_vs_autograd(c)
+
+
 def _step_vjp_vs_autograd(c):
     O = oracle.Oracle(c)
     q = O.prim_to_cons(c.w)
