@@ -36,7 +36,8 @@ def _envelope(c, q, dts, nsteps):
     return bound
 
 
-@pytest.mark.parametrize("kind", ["bubbles", "random", "random-weno-z", "random-weno-m", "random-hll"])
+@pytest.mark.parametrize("kind", ["bubbles", "random", "random-weno-z", "random-weno-m", "random-hll",
+                                  "random-low-mach", "random-weno-m-hll-low-mach"])
 def test_fp32_form_within_float_envelope(kind):
     from paper_2503_07953_amd.solver import Solver
     if kind == "bubbles":
@@ -45,8 +46,9 @@ def test_fp32_form_within_float_envelope(kind):
     else:
         c = W.random_case(3, (40, 36, 30), nf=2, seed=5, bc=(W.EXTRAP, W.SLIPWALL, W.PERIODIC), speed=100.0)
         nsteps = 10
-        c.weno_variant = {"random": 0, "random-weno-z": 1, "random-weno-m": 3, "random-hll": 0}[kind]
-        c.riemann = 1 if kind == "random-hll" else 0
+        c.weno_variant = 1 if "weno-z" in kind else 3 if "weno-m" in kind else 0
+        c.riemann = 1 if "hll" in kind else 0
+        c.low_mach = 1 if "low-mach" in kind else 0
     O = oracle.Oracle(c)
     q = O.prim_to_cons(c.w)
     dts = O.run(q, nsteps, cfl=0.5)
