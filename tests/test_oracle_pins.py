@@ -515,14 +515,25 @@ def test_hllc_flags_nonphysical_state():
 # --------------------------------------------------------------------------
 # C-2 / C-6: RHS assembly, ghost layers, invariances
 # --------------------------------------------------------------------------
+# every setting of the options (reconstruction weights, face solver, low-Mach
+# correction): the symmetries below hold bitwise whichever the setting
+OPTIONS = [(0, 0, 0), (1, 0, 0), (2, 0, 0), (3, 0, 0), (0, 1, 0), (0, 0, 1), (3, 1, 1), (2, 1, 1), (1, 0, 1)]
+
+
+def _set_options(c, opt):
+    c.weno_variant, c.riemann, c.low_mach = opt
+    return c
+
+
+@pytest.mark.parametrize("opt", OPTIONS)
 @pytest.mark.parametrize("bc", [W.PERIODIC, W.EXTRAP, W.SLIPWALL])
-def test_uniform_state_zero_rhs(bc):
+def test_uniform_state_zero_rhs(bc, opt):
     n = (10, 9, 8)
     w = np.zeros((8,) + n[::-1])
     w[0], w[1], w[2], w[3], w[4], w[5], w[6], w[7] = 300.0, 0.7, 0.0, 0.0, 0.0, 2e5, 0.3, 0.7
     if bc != W.SLIPWALL:
         w[2], w[3], w[4] = 12.0, -5.0, 3.0
-    c = W.Case("u", 3, n, 2, (0.1, 0.1, 0.1), (6.12, 1.4), (3.43e8, 0.0), (bc,) * 3, (bc,) * 3, w)
+    c = _set_options(W.Case("u", 3, n, 2, (0.1, 0.1, 0.1), (6.12, 1.4), (3.43e8, 0.0), (bc,) * 3, (bc,) * 3, w), opt)
     O = oracle.Oracle(c)
     r = O.rhs(O.prim_to_cons(w))
     assert np.all(r == 0.0)
@@ -536,14 +547,15 @@ def test_periodic_telescoping_conservation():
         assert abs(r[v].sum()) <= 1e-13 * np.abs(r[v]).sum()
 
 
-def test_transpose_xy_bitwise():
-    c = W.random_case(2, (20, 20), nf=2, seed=9, bc=(W.SLIPWALL, W.EXTRAP))
+@pytest.mark.parametrize("opt", OPTIONS)
+def test_transpose_xy_bitwise(opt):
+    c = _set_options(W.random_case(2, (20, 20), nf=2, seed=9, bc=(W.SLIPWALL, W.EXTRAP)), opt)
     O = oracle.Oracle(c)
     q = O.prim_to_cons(c.w)
     r = O.rhs(q)
     qt = q.transpose(0, 1, 3, 2)[[0, 1, 3, 2, 4, 5, 6]].copy()
-    ct = W.Case("t", 2, (20, 20, 1), 2, c.dx, c.gamma, c.pi_inf, (W.EXTRAP, W.SLIPWALL, 1),
-                (W.EXTRAP, W.SLIPWALL, 1), qt)
+    ct = _set_options(W.Case("t", 2, (20, 20, 1), 2, c.dx, c.gamma, c.pi_inf, (W.EXTRAP, W.SLIPWALL, 1),
+                             (W.EXTRAP, W.SLIPWALL, 1), qt), opt)
     rt = oracle.Oracle(ct).rhs(qt)
     assert np.array_equal(rt, r.transpose(0, 1, 3, 2)[[0, 1, 3, 2, 4, 5, 6]])
 
@@ -564,8 +576,9 @@ def test_one_d_embedding_bitwise():
     assert np.all(r2[3] == 0.0)
 
 
-def test_periodic_shift_bitwise():
-    c = W.random_case(2, (24, 16), nf=2, seed=12, bc=(W.PERIODIC, W.PERIODIC))
+@pytest.mark.parametrize("opt", OPTIONS)
+def test_periodic_shift_bitwise(opt):
+    c = _set_options(W.random_case(2, (24, 16), nf=2, seed=12, bc=(W.PERIODIC, W.PERIODIC)), opt)
     O = oracle.Oracle(c)
     q = O.prim_to_cons(c.w)
     r = O.rhs(q)
@@ -573,8 +586,9 @@ def test_periodic_shift_bitwise():
     assert np.array_equal(O.rhs(qs), np.roll(r, (5, -3), axis=(3, 2)))
 
 
-def test_slip_wall_equals_mirror_doubled_domain():
-    c = W.random_case(2, (16, 12), nf=2, seed=13, bc=(W.EXTRAP, W.EXTRAP))
+@pytest.mark.parametrize("opt", OPTIONS)
+def test_slip_wall_equals_mirror_doubled_domain(opt):
+    c = _set_options(W.random_case(2, (16, 12), nf=2, seed=13, bc=(W.EXTRAP, W.EXTRAP)), opt)
     c.bc_hi = (W.SLIPWALL, W.EXTRAP, W.EXTRAP)
     O = oracle.Oracle(c)
     q = O.prim_to_cons(c.w)
@@ -582,7 +596,7 @@ def test_slip_wall_equals_mirror_doubled_domain():
     mirror = q[:, :, :, ::-1].copy()
     mirror[2] = -mirror[2]
     qd = np.ascontiguousarray(np.concatenate([q, mirror], axis=3))
-    cd = W.Case("d", 2, (32, 12, 1), 2, c.dx, c.gamma, c.pi_inf, (1, 1, 1), (1, 1, 1), qd)
+    cd = _set_options(W.Case("d", 2, (32, 12, 1), 2, c.dx, c.gamma, c.pi_inf, (1, 1, 1), (1, 1, 1), qd), opt)
     rd = oracle.Oracle(cd).rhs(qd)
     assert np.array_equal(rd[:, :, :, :16], r)
 
