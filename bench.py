@@ -238,7 +238,7 @@ def periodic_slab_leg(n=512, steps=100, warmup=2):
 
 
 def paper_shape_grind(steps=20, warmup=3):
-    """The paper's single-device benchmark shape (Sec. 5: 3D, two fluids, 8
+    """The paper's single-device benchmark shape (Sec. 4.3.2: 3D, two fluids, 8
     PDEs) at 158^3 and 200^3 cells, from the bubble-cloud generator (seed 5):
     FP64 and FP32 grind, also per PDE (the paper's unit), each the median of
     three runs of warmup + steps CFL steps from the initial state."""

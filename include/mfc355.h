@@ -115,7 +115,10 @@ typedef struct {
   double dx[3];        /* uniform spacing per axis (> 0 on active axes) */
   double gamma[2];     /* stiffened-gas gamma_i > 1 per fluid (Sec. 2.2) */
   double pi_inf[2];    /* stiffened-gas pi_inf,i >= 0 per fluid */
-  double weno_eps;     /* WENO smoothness regularization, > 0 (1e-6) */
+  double weno_eps;     /* WENO smoothness regularization, 1e-30 <= eps < 1e300
+                          (1e-6); smaller values are rejected with MFC_ERR_ARG
+                          because the double reconstruction normalizes through
+                          a product of eight terms of size >= 4 eps */
   int32_t weno_variant; /* MFC_WENO_JS, MFC_WENO_Z, MFC_TENO or MFC_WENO_M */
   int32_t riemann_solver; /* MFC_HLLC (0) or MFC_HLL */
   int32_t low_mach;       /* MFC_LOW_MACH_NONE (0) or MFC_LOW_MACH_THORNBER */

@@ -53,6 +53,7 @@ class OrcProblem(ctypes.Structure):
         ("weno_variant", ctypes.c_int32),
         ("riemann", ctypes.c_int32),
         ("low_mach", ctypes.c_int32),
+        ("model", ctypes.c_int32),
     ]
 
 
@@ -83,6 +84,7 @@ def lib():
             "orc_hllc": (ctypes.c_int, [P, ctypes.c_int, dp, dp, dp, dp]),
             "orc_hll": (ctypes.c_int, [P, ctypes.c_int, dp, dp, dp, dp]),
             "orc_thornber": (None, [P, ctypes.c_int, dp, dp]),
+            "orc_kapila_K": (ctypes.c_double, [P, dp]),
             "orc_rhs": (ctypes.c_int, [P, dp, dp]),
             "orc_rhs_cells": (ctypes.c_int, [P, dp, ctypes.c_int64, i64p, dp]),
             "orc_max_signal": (ctypes.c_int, [P, dp, dp]),
@@ -104,7 +106,7 @@ def lib():
 
 
 def problem(ndim, n, num_fluids, dx, gamma, pi_inf, bc_lo, bc_hi, weno_eps=1e-6, weno_variant=0,
-            riemann=0, low_mach=0) -> OrcProblem:
+            riemann=0, low_mach=0, model=0) -> OrcProblem:
     P = OrcProblem()
     P.ndim = ndim
     n = tuple(n) + (1,) * (3 - len(n))
@@ -121,6 +123,7 @@ def problem(ndim, n, num_fluids, dx, gamma, pi_inf, bc_lo, bc_hi, weno_eps=1e-6,
     P.weno_variant = int(weno_variant)
     P.riemann = int(riemann)
     P.low_mach = int(low_mach)
+    P.model = int(model)
     return P
 
 
@@ -243,6 +246,11 @@ class Oracle:
         wr = np.array(wr, dtype=np.float64)
         self.L.orc_thornber(ctypes.byref(self.P), d, _dp(wl), _dp(wr))
         return wl, wr
+
+    def kapila_K(self, w):
+        """Kapila's K (Sec. 2.1.1) of one primitive cell state w (neq values)."""
+        w = np.ascontiguousarray(w, dtype=np.float64)
+        return self.L.orc_kapila_K(ctypes.byref(self.P), _dp(w))
 
     def hll(self, d, wl, wr):
         """HLL face flux and face velocity (Sec. 3.2.2)."""

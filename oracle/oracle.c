@@ -50,7 +50,9 @@ typedef struct {
   double weno_eps;
   int32_t weno_variant; /* 0: WENO5-JS (Sec. 3.2.1), 1: WENO5-Z, 2: TENO5 (Sec. 4.2.2), 3: WENO5-M (Sec. 3.2.1) */
   int32_t riemann;      /* 0: HLLC, 1: HLL (Sec. 3.2.2) */
-  int32_t low_mach;     /* 0: none, 1: the Thornber et al. velocity correction (Sec. 4.2, low-Mach treatment) */
+  int32_t low_mach;     /* 0: none, 1: the Thornber et al. velocity correction, 2: the anti-dissipation
+                           pressure correction of Chen et al. (HLLC only) (Sec. 4.2.4) */
+  int32_t model;        /* 0: Allaire (K = 0), 1: Kapila, K div u on the alpha rows (Sec. 2.1.1) */
 } orc_problem;
 
 /* ------------------------------------------------------------------------ */
@@ -87,7 +89,10 @@ int orc_validate(const orc_problem* P) {
   if (!(P->weno_eps > 0)) return ORC_ERR_ARG;
   if (P->weno_variant < 0 || P->weno_variant > 3) return ORC_ERR_ARG;
   if (P->riemann < 0 || P->riemann > 1) return ORC_ERR_ARG;
-  if (P->low_mach < 0 || P->low_mach > 1) return ORC_ERR_ARG;
+  if (P->low_mach < 0 || P->low_mach > 2) return ORC_ERR_ARG;
+  if (P->low_mach == 2 && P->riemann != 0) return ORC_ERR_ARG;
+  if (P->model < 0 || P->model > 1) return ORC_ERR_ARG;
+  if (P->model == 1 && P->num_fluids != 2) return ORC_ERR_ARG;
   return ORC_OK;
 }
 
@@ -332,7 +337,7 @@ double orc_teno5_right(const double* f, double eps, double ct) {
 /* Riemann problem yields F and u at the face).                             */
 /* Readings:                                                                */
 /*   wave speeds: S_L = min(u_L - c_L, u_R - c_R), S_R = max(u_L + c_L,     */
-/*     u_R + c_R) (the form printed for HLLD in Sec. 4.2.6); ties take the  */
+/*     u_R + c_R) (the form printed for HLLD in Sec. 4.2.5); ties take the  */
 /*     first argument;                                                      */
 /*   contact speed S* from continuity of normal velocity and pressure;      */
 /*   regions: S_L >= 0 -> left; S* >= 0 -> left star; S_R > 0 -> right star;*/
@@ -405,6 +410,23 @@ int orc_hllc(const orc_problem* P, int d, const double* WL, const double* WR, do
                  (L.rho * (SL - L.un) - R.rho * (SR - R.un));
   double Us[NEQ_MAX];
   const double* alpha_side;
+  /* Anti-dissipation pressure correction of Chen et al. (Sec. 4.2.4), added
+   * to both star-region fluxes:
+   *   p_d = rho_L rho_R (S_L - u_L)(S_R - u_R)(u_R - u_L)
+   *         / (rho_R (S_R - u_R) - rho_L (S_L - u_L)),
+   *   APC = (z - 1) p_d on the face-normal momentum, (z - 1) p_d S* on the
+   *   energy, with z = min(max(|u_L|/c_L, |u_R|/c_R), 1) (the Mach number of
+   *   the low-Mach section; sound speeds of the reconstructed states). */
+  double apc_mom = 0.0, apc_E = 0.0;
+  if (P->low_mach == 2) {
+    double mL = fabs(L.un) / L.c, mR = fabs(R.un) / R.c;
+    double z = (mL >= mR) ? mL : mR;
+    if (z > 1.0) z = 1.0;
+    double pd = L.rho * R.rho * (SL - L.un) * (SR - R.un) * (R.un - L.un) /
+                (R.rho * (SR - R.un) - L.rho * (SL - L.un));
+    apc_mom = (z - 1.0) * pd;
+    apc_E = (z - 1.0) * pd * Sstar;
+  }
   if (SL >= 0.0) {
     for (int v = 0; v < ncons; ++v) F[v] = L.F[v];
     *uf = L.un;
@@ -412,11 +434,19 @@ int orc_hllc(const orc_problem* P, int d, const double* WL, const double* WR, do
   } else if (Sstar >= 0.0) {
     star_state(P, d, WL, &L, SL, Sstar, Us);
     for (int v = 0; v < ncons; ++v) F[v] = L.F[v] + SL * (Us[v] - L.U[v]);
+    if (P->low_mach == 2) {
+      F[row_mom(P, d)] = F[row_mom(P, d)] + apc_mom;
+      F[row_E(P)] = F[row_E(P)] + apc_E;
+    }
     *uf = Sstar;
     alpha_side = WL;
   } else if (SR > 0.0) {
     star_state(P, d, WR, &R, SR, Sstar, Us);
     for (int v = 0; v < ncons; ++v) F[v] = R.F[v] + SR * (Us[v] - R.U[v]);
+    if (P->low_mach == 2) {
+      F[row_mom(P, d)] = F[row_mom(P, d)] + apc_mom;
+      F[row_E(P)] = F[row_E(P)] + apc_E;
+    }
     *uf = Sstar;
     alpha_side = WR;
   } else {
@@ -541,8 +571,34 @@ static int face_flux(const orc_problem* P, const double* q, int d, const int idx
   return P->riemann == 1 ? orc_hll(P, d, WL, WR, F, uf) : orc_hllc(P, d, WL, WR, F, uf);
 }
 
+/* ------------------------------------------------------------------------ */
+/* Kapila's K (Sec. 2.1.1): the alpha_1 equation of the five-equation model  */
+/* carries K div u with                                                     */
+/*   K = (rho_2 c_2^2 - rho_1 c_1^2) / (rho_1 c_1^2/alpha_1 + rho_2 c_2^2/alpha_2),*/
+/* phasic densities rho_i = (alpha_i rho_i)/alpha_i and phasic sound speeds  */
+/* c_i = sqrt(gamma_i (p + pi_inf,i)/rho_i).  Reading: the printed numerator */
+/* has a plus sign, which would not vanish for two identical fluids; the     */
+/* thermodynamically consistent term (each phase compressed along its own    */
+/* isentrope) has the difference, as written here.  The alpha_2 equation     */
+/* takes -K, so that alpha_1 + alpha_2 is unchanged.  W: primitive state of  */
+/* the cell (cell averages).                                                */
+/* ------------------------------------------------------------------------ */
+double orc_kapila_K(const orc_problem* P, const double* W) {
+  double p = W[row_E(P)];
+  double rc2[2];
+  for (int i = 0; i < 2; ++i) {
+    double alpha = W[row_alpha(P, i)];
+    double rho_i = W[i] / alpha;
+    double c2_i = P->gamma[i] * (p + P->pi_inf[i]) / rho_i;
+    rc2[i] = rho_i * c2_i;
+  }
+  double a1 = W[row_alpha(P, 0)], a2 = W[row_alpha(P, 1)];
+  return (rc2[1] - rc2[0]) / (rc2[0] / a1 + rc2[1] / a2);
+}
+
 /* Contribution of axis d to the RHS of one cell (eq. eqn:rhs with s = 0 and
- * h = -alpha for the Allaire model, K = 0):
+ * h = -alpha for the Allaire model, K = 0; h = -(alpha_i + K_i) with K_1 = K,
+ * K_2 = -K for the Kapila model):
  *   D_v = (F_{m-1/2} - F_{m+1/2}) / dx_d for every row,
  *   plus alpha_cell (u_{m+1/2} - u_{m-1/2}) / dx_d on the alpha rows, where
  *   alpha_cell is the cell-average volume fraction. */
@@ -552,11 +608,22 @@ static void axis_contribution(const orc_problem* P, int d, const double* Flo, do
   int nf = P->num_fluids, neq = orc_num_eqs(P);
   double inv_dx = 1.0 / P->dx[d];
   for (int v = 0; v < neq; ++v) Dv[v] = inv_dx * (Flo[v] - Fhi[v]);
-  if (nf == 2)
+  if (nf == 2) {
+    double K[2] = {0.0, 0.0};
+    if (P->model == 1) {
+      double Wc[NEQ_MAX];
+      cell_cons_to_prim(P, Ucell, Wc);
+      K[0] = orc_kapila_K(P, Wc);
+      K[1] = -K[0];
+    }
     for (int i = 0; i < 2; ++i) {
       int a = row_alpha(P, i);
-      Dv[a] = Dv[a] + Ucell[a] * (inv_dx * (uhi - ulo));
+      if (P->model == 1)
+        Dv[a] = Dv[a] + (Ucell[a] + K[i]) * (inv_dx * (uhi - ulo));
+      else
+        Dv[a] = Dv[a] + Ucell[a] * (inv_dx * (uhi - ulo));
     }
+  }
 }
 
 /* Full RHS: rhs = sum over axes d = 0..D-1 (in that order) of D_d. */

@@ -42,7 +42,7 @@ def sqrt(x):
 
 class Problem:
     def __init__(self, ndim, n, num_fluids, dx, gamma, pi_inf, bc_lo, bc_hi, weno_eps=1e-6, weno_variant=0,
-                 riemann=0, low_mach=0):
+                 riemann=0, low_mach=0, model=0):
         self.ndim = ndim
         self.n = tuple(n) + (1,) * (3 - len(n))
         self.nf = num_fluids
@@ -55,6 +55,7 @@ class Problem:
         self.weno_variant = int(weno_variant)
         self.riemann = int(riemann)
         self.low_mach = int(low_mach)
+        self.model = int(model)
         self.neq = self.nf + ndim + 1 + (2 if self.nf == 2 else 0)
         self.G = [1.0 / (g - 1.0) for g in self.gamma]
         self.P = [g * p / (g - 1.0) for g, p in zip(self.gamma, self.pi_inf)]
@@ -286,6 +287,20 @@ def hllc(P: Problem, d, WL, WR):
 
     FLs = star_flux(WL, L, SL)
     FRs = star_flux(WR, R, SR)
+    if P.low_mach == 2:
+        # anti-dissipation pressure correction of Chen et al. (Sec. 4.2.4) on
+        # both star-region fluxes
+        mL = torch.abs(L["un"]) / L["c"]
+        mR = torch.abs(R["un"]) / R["c"]
+        z = torch.where(mL >= mR, mL, mR)
+        z = torch.where(z > 1.0, torch.ones_like(z), z)
+        pd = L["rho"] * R["rho"] * (SL - L["un"]) * (SR - R["un"]) * (R["un"] - L["un"]) / (
+            R["rho"] * (SR - R["un"]) - L["rho"] * (SL - L["un"]))
+        apc_mom = (z - 1.0) * pd
+        apc_E = (z - 1.0) * pd * Sstar
+        m, e = P.row_mom(d), P.row_E
+        FLs[m], FRs[m] = FLs[m] + apc_mom, FRs[m] + apc_mom
+        FLs[e], FRs[e] = FLs[e] + apc_E, FRs[e] + apc_E
     c1 = SL >= 0.0
     c2 = Sstar >= 0.0
     c3 = SR > 0.0
@@ -365,14 +380,31 @@ def axis_contribution(P: Problem, q, d):
     Dv = inv_dx * (Flo - Fhi)
     if P.nf == 2:
         ulo, uhi = _sl(uf, ax - 1, 0, n), _sl(uf, ax - 1, 1, n)
+        K = kapila_K(P, cons_to_prim(P, q)) if P.model == 1 else None
         rows = []
         for v in range(P.neq):
             if v >= P.row_alpha(0):
-                rows.append(Dv[v] + q[v] * (inv_dx * (uhi - ulo)))
+                if K is None:
+                    rows.append(Dv[v] + q[v] * (inv_dx * (uhi - ulo)))
+                else:
+                    Ki = K if v == P.row_alpha(0) else -K
+                    rows.append(Dv[v] + (q[v] + Ki) * (inv_dx * (uhi - ulo)))
             else:
                 rows.append(Dv[v])
         Dv = torch.stack(rows)
     return Dv
+
+
+def kapila_K(P: Problem, w):
+    """Kapila's K of the alpha_1 equation (Sec. 2.1.1, difference in the
+    numerator) from primitive cell states w; alpha_2 takes -K."""
+    p = w[P.row_E]
+    rc2 = []
+    for i in range(2):
+        rho_i = w[i] / w[P.row_alpha(i)]
+        c2_i = P.gamma[i] * (p + P.pi_inf[i]) / rho_i
+        rc2.append(rho_i * c2_i)
+    return (rc2[1] - rc2[0]) / (rc2[0] / w[P.row_alpha(0)] + rc2[1] / w[P.row_alpha(1)])
 
 
 def rhs(P: Problem, q):

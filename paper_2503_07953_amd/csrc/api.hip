@@ -162,6 +162,10 @@ int ensure_vjp_scratch(mfc_ctx* c) {
   return MFC_OK;
 }
 
+// Smallest accepted WENO eps: (4 eps)^8 stays far above the smallest normal
+// double (2.2e-308) for every eps >= 1e-30.
+constexpr double kMinWenoEps = 1e-30;
+
 bool aligned(const void* p, size_t a) { return (reinterpret_cast<uintptr_t>(p) % a) == 0; }
 
 int check_device(mfc_ctx* c) {
@@ -259,7 +263,10 @@ int mfc_validate(const mfc_problem* p) {
   if (ncell > (1LL << 34)) return MFC_ERR_SHAPE;
   for (int i = 0; i < p->num_fluids; ++i)
     if (!(p->gamma[i] > 1.0) || !(p->pi_inf[i] >= 0.0) || !(p->pi_inf[i] < 1e300)) return MFC_ERR_ARG;
-  if (!(p->weno_eps > 0.0)) return MFC_ERR_ARG;
+  // the double reconstructions normalize through products of up to eight
+  // smoothness indicators, each at least 4 eps: eps below kMinWenoEps would
+  // let that product underflow on flat data
+  if (!(p->weno_eps >= kMinWenoEps) || !(p->weno_eps < 1e300)) return MFC_ERR_ARG;
   if (p->weno_variant < MFC_WENO_JS || p->weno_variant > MFC_WENO_M) return MFC_ERR_UNSUPPORTED;
   if (p->riemann_solver != MFC_HLLC && p->riemann_solver != MFC_HLL) return MFC_ERR_UNSUPPORTED;
   if (p->low_mach != MFC_LOW_MACH_NONE && p->low_mach != MFC_LOW_MACH_THORNBER) return MFC_ERR_UNSUPPORTED;

@@ -4,7 +4,7 @@
 // Every function here is templated on the grid (fluid count NF, dimension D)
 // so that row indices and loop trip counts are compile-time constants: the
 // problem-specialized code generation the paper gets from its "case
-// optimization" (Sec. 4.3.3) comes from C++ templates instead.
+// optimization" (Sec. 4.3.6) comes from C++ templates instead.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -172,9 +172,12 @@ __host__ __device__ __forceinline__ void weno5_js(double a, double b, double c, 
   fr = c + nr * (dl * inv);
 }
 
-// FP32: the same difference form; products of t's would overflow float for
-// pressure-sized data, so the weights use hardware reciprocals of t_k
-// (v_rcp_f32, ~1 ulp) and each biased value its own normalization.
+// FP32: the same difference form.  Squared indicators overflow float for
+// pressure jumps of a few GPa (s ~ 1e19, s^2 > 3.4e38), so the weights are
+// formed from the ratios s_min/s_k in (0, 1] (hardware reciprocals, ~1 ulp):
+// a_k = (s_min/s_k)^2 is d_k/(eps + beta_k)^2 up to the common factor s_min^2,
+// which the normalization removes, and the largest a_k is exactly 1.  Each
+// biased value has its own normalization.
 __device__ __forceinline__ void weno5_js(float a, float b, float c, float d, float e, float eps,
                                          float& fl, float& fr) {
   const float D0 = b - a, D1 = c - b, D2 = d - c, D3 = e - d;
@@ -185,9 +188,10 @@ __device__ __forceinline__ void weno5_js(float a, float b, float c, float d, flo
   const float s0 = e4 + ((13.0f / 3.0f) * u0 * u0 + v0 * v0);
   const float s1 = e4 + ((13.0f / 3.0f) * u1 * u1 + v1 * v1);
   const float s2 = e4 + ((13.0f / 3.0f) * u2 * u2 + v2 * v2);
-  const float a0 = __builtin_amdgcn_rcpf(s0 * s0);
-  const float a1 = __builtin_amdgcn_rcpf(s1 * s1);
-  const float a2 = __builtin_amdgcn_rcpf(s2 * s2);
+  const float sm = fminf(s0, fminf(s1, s2));
+  const float a0 = sq(sm * __builtin_amdgcn_rcpf(s0));
+  const float a1 = sq(sm * __builtin_amdgcn_rcpf(s1));
+  const float a2 = sq(sm * __builtin_amdgcn_rcpf(s2));
   const float l0 = 5.0f * D1 - 2.0f * D0, l1 = D1 + 2.0f * D2, l2 = 4.0f * D2 - D3;
   const float r0 = 2.0f * D3 - 5.0f * D2, r1 = -(D2 + 2.0f * D1), r2 = D0 - 4.0f * D1;
   const float w1 = 0.6f * a1;
@@ -376,8 +380,8 @@ __host__ __device__ __forceinline__ void weno5_m(double a, double b, double c, d
   fr = c + (er0 * r0 + er1 * r1 + er2 * r2) * (hl * inv2);
 }
 
-// FP32 WENO5-M: the JS weights of the float weno5_js (hardware reciprocals of
-// t_k), normalized, mapped in float and normalized per side.
+// FP32 WENO5-M: the JS weights of the float weno5_js (ratios s_min/s_k, so
+// that nothing overflows), normalized, mapped in float and normalized per side.
 __device__ __forceinline__ void weno5_m(float a, float b, float c, float d, float e, float eps, float& fl,
                                         float& fr) {
   const float D0 = b - a, D1 = c - b, D2 = d - c, D3 = e - d;
@@ -388,9 +392,10 @@ __device__ __forceinline__ void weno5_m(float a, float b, float c, float d, floa
   const float s0 = e4 + ((13.0f / 3.0f) * u0 * u0 + v0 * v0);
   const float s1 = e4 + ((13.0f / 3.0f) * u1 * u1 + v1 * v1);
   const float s2 = e4 + ((13.0f / 3.0f) * u2 * u2 + v2 * v2);
-  const float a0 = __builtin_amdgcn_rcpf(s0 * s0);
-  const float a1 = __builtin_amdgcn_rcpf(s1 * s1);
-  const float a2 = __builtin_amdgcn_rcpf(s2 * s2);
+  const float sm = fminf(s0, fminf(s1, s2));
+  const float a0 = sq(sm * __builtin_amdgcn_rcpf(s0));
+  const float a1 = sq(sm * __builtin_amdgcn_rcpf(s1));
+  const float a2 = sq(sm * __builtin_amdgcn_rcpf(s2));
   const float w1 = 0.6f * a1;
   const float wl0 = 0.1f * a0, wl2 = 0.3f * a2;
   const float wr0 = 0.1f * a2, wr2 = 0.3f * a0;
@@ -464,7 +469,7 @@ __device__ __forceinline__ void weno5(T a, T b, T c, T d, T e, T eps, T& fl, T& 
 // of every row and the face velocity u_f.  T is the flux arithmetic type;
 // sound speeds and the wave speeds S_L, S_R, S* are always double.
 //   S_L = min(u_L - c_L, u_R - c_R), S_R = max(u_L + c_L, u_R + c_R) (the form
-//   printed for the HLLD solver, Sec. 4.2.6), ties to the first argument;
+//   printed for the HLLD solver, Sec. 4.2.5), ties to the first argument;
 //   regions: S_L >= 0 left; S* >= 0 left star; S_R > 0 right star; else right;
 //   volume fractions are carried by the contact: flux alpha_K u_f.
 // Returns true when a side has c^2 <= 0 or a flux is not finite.

@@ -24,8 +24,11 @@ class Solver:
     """Owns one mfc_ctx.  `precision` is "fp64" or "fp32" (the mixed FP32 form)."""
 
     def __init__(self, ndim, n, num_fluids, dx, gamma, pi_inf, bc_lo, bc_hi, weno_eps=1e-6,
-                 precision="fp64", device="cuda", weno_variant=0, riemann=0, low_mach=0):
+                 precision="fp64", device="cuda", weno_variant=0, riemann=0, low_mach=0, model=0):
         self.lib = L.load()
+        if model != 0 or low_mach == 2:
+            raise L.MfcError(L.MFC_ERR_UNSUPPORTED, "the Kapila model and the APC correction are not in this "
+                                                    "library version")
         self.precision = precision
         prec = L.MFC_FP64 if precision == "fp64" else L.MFC_FP32_MIXED
         self.prob = L.make_problem(ndim, n, num_fluids, dx, gamma, pi_inf, bc_lo, bc_hi, weno_eps, prec, weno_variant,

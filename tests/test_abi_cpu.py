@@ -66,6 +66,10 @@ def test_num_eqs(L):
     (dict(bc_lo=(0, 1), bc_hi=(1, 1)), -1),
     (dict(bc_lo=(5, 1)), -1),
     (dict(weno_eps=0.0), -1),
+    (dict(weno_eps=1e-40), -1),
+    (dict(weno_eps=9.9e-31), -1),
+    (dict(weno_eps=1e-30), 0),
+    (dict(weno_eps=float("inf")), -1),
     (dict(weno_variant=1), 0),
     (dict(weno_variant=2), 0),
     (dict(weno_variant=3), 0),

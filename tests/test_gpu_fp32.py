@@ -16,7 +16,7 @@ import torch
 
 import oracle
 import workloads as W
-from helpers import conservative_errors
+from helpers import grouped_errors
 
 pytestmark = pytest.mark.gpu
 EPS32 = 2.0 ** -24
@@ -57,7 +57,7 @@ def test_fp32_form_within_float_envelope(kind):
     S.run(q32, nsteps, cfl=0.5)
     S.check()
     got = q32.double().cpu().numpy()
-    err = conservative_errors(got, q, 2, 3)
+    err = grouped_errors(got, q, 2, 3)
     bound = _envelope(c, q, dts, nsteps)
     _say(kind, "errors", err, "bounds", bound)
     assert np.all(err <= bound), (err, bound)
@@ -84,7 +84,7 @@ def test_fp32_teno_bubbles_within_envelope_but_at_flips():
     S.check()
     got = q32.double().cpu().numpy()
     bound = _envelope(c, q, dts, nsteps)
-    err = conservative_errors(got, q, 2, 3)
+    err = grouped_errors(got, q, 2, 3)
     # per-cell errors on each field's scale (momentum as one vector)
     d = np.abs(got - q)
     scale = np.abs(q).reshape(q.shape[0], -1).max(axis=1)
@@ -145,3 +145,46 @@ def test_fp32_rhs_and_conversions_track_fp64():
     s64 = O.max_signal(q)
     s32 = S.max_signal(q32).item()
     assert abs(s32 / s64 - 1) <= 1e-6
+
+
+@pytest.mark.parametrize("variant", [0, 3])
+def test_fp32_gigapascal_jump_stays_finite_and_tracks_fp64(variant):
+    """A 4.5 GPa pressure jump in water spread over two cells: the squared
+    smoothness indicators of the pressure row exceed the float range, so the
+    FP32 weights are formed from the ratios s_min / s_k.  The FP32 RHS must be
+    finite and agree with the FP64 oracle on the flux scale (1e-4, as for the
+    other FP32 RHS checks), and five CFL steps must stay finite and within
+    1e-4 of the oracle per field (WENO5-JS and WENO5-M)."""
+    from helpers import rate_errors
+    from paper_2503_07953_amd.solver import Solver
+    n = 128
+    dx = 1.0 / n
+    x = (np.arange(n) + 0.5) * dx
+    p = np.where(x < 0.5, 1e5, 4.5e9)
+    p[n // 2 - 1] = 1e5 + (4.5e9 - 1e5) / 3
+    p[n // 2] = 1e5 + 2 * (4.5e9 - 1e5) / 3
+    aw = np.full(n, 1.0 - W.ALPHA_FLOOR)
+    aw[: n // 4] = W.ALPHA_FLOOR  # an air column as well
+    w = W._two_fluid_w(aw, 1000.0, 1.0, [np.zeros(n)], p).reshape(6, 1, 1, n)
+    c = W.Case("gpa_jump", 1, (n, 1, 1), 2, (dx, 1.0, 1.0), (6.12, 1.4), (3.43e8, 0.0),
+               (W.EXTRAP,) * 3, (W.EXTRAP,) * 3, w)
+    c.weno_variant = variant
+    O = oracle.Oracle(c)
+    q = O.prim_to_cons(c.w)
+    ref = O.rhs(q)
+    S = Solver.from_case(c, precision="fp32")
+    r = S.rhs(S.to_device(q)).double().cpu().numpy()
+    S.check()
+    assert np.isfinite(r).all()
+    err = rate_errors(r, ref, q, O.max_signal(q), 2, 1)
+    _say("GPa jump rhs errors", variant, err)
+    assert err.max() <= 1e-4, err
+    q32 = S.to_device(q)
+    S.run(q32, 5, cfl=0.5)
+    S.check()
+    O.run(q, 5, cfl=0.5)
+    got = q32.double().cpu().numpy()
+    assert np.isfinite(got).all()
+    e = grouped_errors(got, q, 2, 1)
+    _say("GPa jump 5-step errors", variant, e)
+    assert e.max() <= 1e-4, e

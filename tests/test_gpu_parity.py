@@ -114,10 +114,20 @@ def test_cfl_steps_match_oracle(nd, n, nf, bc, nsteps):
     assert err.max() <= TOL, err
 
 
-def _variant_steps_match(c, nf, nd, flux_scale=False):
+def _quiet_components(c):
+    """Momentum components that stay zero in exact arithmetic over the first
+    few steps of the small benchmark flows: the planar shock (or pulse) has not
+    reached the air inclusions, which sit at rest in uniform pressure, so no
+    momentum arises across the wave (y in 2D, y and z in 3D)."""
+    return (1,) if c.ndim == 2 else (1, 2)
+
+
+def _variant_steps_match(c, nf, nd, flux_scale=False, zero_mom=()):
     """flux_scale: compare the RHS on the flux scale of each field (flows at
     rest in uniform pressure, where the exact alpha RHS is zero and both sides
-    return rounding noise), else on the scale of the RHS itself."""
+    return rounding noise), else on the scale of the RHS itself.  zero_mom:
+    momentum components that are zero in exact arithmetic over the 5 steps
+    (measured on the momentum-vector scale)."""
     O = oracle.Oracle(c)
     q = O.prim_to_cons(c.w)
     S = _solver(c)
@@ -136,11 +146,11 @@ def _variant_steps_match(c, nf, nd, flux_scale=False):
     rng = np.random.default_rng(17)
     q_ref = q.copy()
     O.run(q_ref, 5, cfl=0.5)
-    spread = np.zeros(nf + 1 + 1 + (nf if nf == 2 else 0))
+    spread = np.zeros(c.neq)
     for _ in range(2):
         qp = q * (1.0 + rng.choice([-1.0, 0.0, 1.0], size=q.shape) * EPS)
         O.run(qp, 5, cfl=0.5)
-        spread = np.maximum(spread, conservative_errors(qp, q_ref, nf, nd))
+        spread = np.maximum(spread, conservative_errors(qp, q_ref, nf, nd, zero_mom))
     bar = np.maximum(TOL, 4 * spread)
     dts = O.run(q, 5, cfl=0.5)
     dt = torch.zeros(1, dtype=torch.float64, device="cuda")
@@ -150,7 +160,7 @@ def _variant_steps_match(c, nf, nd, flux_scale=False):
         gdts.append(dt.item())
     S.check()
     assert np.allclose(gdts, dts, rtol=1e-13, atol=0)
-    err = conservative_errors(qd.cpu().numpy(), q, nf, nd)
+    err = conservative_errors(qd.cpu().numpy(), q, nf, nd, zero_mom)
     _say("errors", err, "bar", bar)
     assert np.all(err <= bar), (err, bar)
 
@@ -181,7 +191,7 @@ def test_weno_variants_two_fluid_flows_match_oracle(name, variant):
     else:
         c = W.bubble_cloud(64, nbub=6, slab=8)
     c.weno_variant = variant
-    _variant_steps_match(c, 2, c.ndim, flux_scale=True)
+    _variant_steps_match(c, 2, c.ndim, flux_scale=True, zero_mom=_quiet_components(c))
 
 
 @pytest.mark.parametrize("case", [CASES[0], CASES[1], CASES[3], CASES[5], CASES[6], CASES[7]])
@@ -199,7 +209,7 @@ def test_hll_two_fluid_flows_match_oracle(name):
     _say("hll", name)
     c = W.shock_cylinder(96) if name.startswith("shock") else W.bubble_cloud(64, nbub=6, slab=8)
     c.riemann = 1
-    _variant_steps_match(c, 2, c.ndim, flux_scale=True)
+    _variant_steps_match(c, 2, c.ndim, flux_scale=True, zero_mom=_quiet_components(c))
 
 
 def test_hll_differs_from_hllc():

@@ -57,7 +57,8 @@ class Case:
     weno_eps: float = 1e-6
     weno_variant: int = 0   # 0: WENO5-JS, 1: WENO5-Z, 2: TENO5, 3: WENO5-M
     riemann: int = 0        # 0: HLLC, 1: HLL
-    low_mach: int = 0       # 0: none, 1: Thornber et al. velocity correction
+    low_mach: int = 0       # 0: none, 1: Thornber et al. velocity correction, 2: Chen et al. APC
+    model: int = 0          # 0: Allaire (K = 0), 1: Kapila (K div u on the alpha rows)
     extra: dict = field(default_factory=dict)
 
     @property
@@ -74,7 +75,7 @@ class Case:
                     dx=tuple(self.dx), gamma=tuple(self.gamma),
                     pi_inf=tuple(self.pi_inf), bc_lo=tuple(self.bc_lo),
                     bc_hi=tuple(self.bc_hi), weno_eps=self.weno_eps, weno_variant=self.weno_variant,
-                    riemann=self.riemann, low_mach=self.low_mach)
+                    riemann=self.riemann, low_mach=self.low_mach, model=self.model)
 
 
 def _pad3(t, fill):
