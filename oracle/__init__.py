@@ -54,6 +54,7 @@ class OrcProblem(ctypes.Structure):
         ("riemann", ctypes.c_int32),
         ("low_mach", ctypes.c_int32),
         ("model", ctypes.c_int32),
+        ("faces", ctypes.POINTER(ctypes.c_double) * 3),
     ]
 
 
@@ -85,6 +86,8 @@ def lib():
             "orc_hll": (ctypes.c_int, [P, ctypes.c_int, dp, dp, dp, dp]),
             "orc_thornber": (None, [P, ctypes.c_int, dp, dp]),
             "orc_kapila_K": (ctypes.c_double, [P, dp]),
+            "orc_nu_stencil": (None, [dp, dp, dp, dp, dp, dp, dp]),
+            "orc_weno5_nu": (None, [dp, dp, ctypes.c_double, dp, dp]),
             "orc_rhs": (ctypes.c_int, [P, dp, dp]),
             "orc_rhs_cells": (ctypes.c_int, [P, dp, ctypes.c_int64, i64p, dp]),
             "orc_max_signal": (ctypes.c_int, [P, dp, dp]),
@@ -106,8 +109,19 @@ def lib():
 
 
 def problem(ndim, n, num_fluids, dx, gamma, pi_inf, bc_lo, bc_hi, weno_eps=1e-6, weno_variant=0,
-            riemann=0, low_mach=0, model=0) -> OrcProblem:
+            riemann=0, low_mach=0, model=0, faces=None) -> OrcProblem:
+    """faces: per axis None (uniform dx) or the n + 1 face coordinates of a
+    non-uniform grid.  The arrays are kept on the returned struct."""
     P = OrcProblem()
+    P._faces = []
+    for d in range(3):
+        f = None if faces is None or d >= len(faces) else faces[d]
+        if f is None:
+            P.faces[d] = ctypes.POINTER(ctypes.c_double)()
+        else:
+            a = np.ascontiguousarray(f, dtype=np.float64)
+            P._faces.append(a)
+            P.faces[d] = a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
     P.ndim = ndim
     n = tuple(n) + (1,) * (3 - len(n))
     for d in range(3):
@@ -260,6 +274,31 @@ class Oracle:
         uf = ctypes.c_double()
         rc = self.L.orc_hll(ctypes.byref(self.P), d, _dp(wl), _dp(wr), _dp(F), ctypes.byref(uf))
         return F, uf.value, rc
+
+
+def nu_stencil(h, f=None):
+    """Fifth-order reconstruction quantities on a non-uniform grid (Sec. 4.2.2)
+    for the centre of five cells of widths h (and averages f): candidates at
+    the right and left face, smoothness indicators, ideal weights at both
+    faces (the first three are None without f)."""
+    h = np.ascontiguousarray(h, dtype=np.float64)
+    out = [np.zeros(3) for _ in range(5)]
+    fp = _dp(np.ascontiguousarray(f, dtype=np.float64)) if f is not None else None
+    lib().orc_nu_stencil(fp, _dp(h), *[_dp(o) for o in out])
+    qR, qL, beta, dR, dL = out
+    if f is None:
+        return None, None, None, dR, dL
+    return qR, qL, beta, dR, dL
+
+
+def weno5_nu(f, h, eps=1e-6):
+    """WENO5-JS on a non-uniform grid: (value at the right face, value at the
+    left face) of the centre of five cells with widths h and averages f."""
+    f = np.ascontiguousarray(f, dtype=np.float64)
+    h = np.ascontiguousarray(h, dtype=np.float64)
+    a, b = ctypes.c_double(), ctypes.c_double()
+    lib().orc_weno5_nu(_dp(f), _dp(h), eps, ctypes.byref(a), ctypes.byref(b))
+    return a.value, b.value
 
 
 def num_threads() -> int:

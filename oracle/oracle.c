@@ -53,6 +53,8 @@ typedef struct {
   int32_t low_mach;     /* 0: none, 1: the Thornber et al. velocity correction, 2: the anti-dissipation
                            pressure correction of Chen et al. (HLLC only) (Sec. 4.2.4) */
   int32_t model;        /* 0: Allaire (K = 0), 1: Kapila, K div u on the alpha rows (Sec. 2.1.1) */
+  const double* faces[3]; /* per axis: NULL (uniform spacing dx) or the n + 1 cell-face coordinates of a
+                             non-uniform grid, strictly increasing (Sec. 4.2.2); WENO5-JS only */
 } orc_problem;
 
 /* ------------------------------------------------------------------------ */
@@ -93,6 +95,13 @@ int orc_validate(const orc_problem* P) {
   if (P->low_mach == 2 && P->riemann != 0) return ORC_ERR_ARG;
   if (P->model < 0 || P->model > 1) return ORC_ERR_ARG;
   if (P->model == 1 && P->num_fluids != 2) return ORC_ERR_ARG;
+  for (int d = 0; d < 3; ++d) {
+    if (!P->faces[d]) continue;
+    if (d >= P->ndim || P->weno_variant != 0) return ORC_ERR_ARG;
+    for (int i = 0; i < P->n[d]; ++i)
+      if (!(P->faces[d][i + 1] > P->faces[d][i]) || !isfinite(P->faces[d][i + 1] - P->faces[d][i]))
+        return ORC_ERR_ARG;
+  }
   return ORC_OK;
 }
 
@@ -201,6 +210,17 @@ static void load_cons(const orc_problem* P, const double* q, int d, const int id
   int64_t c = ((int64_t)id[2] * P->n[1] + id[1]) * P->n[0] + id[0];
   for (int v = 0; v < neq; ++v) U[v] = q[v * nc + c];
   if (flip) U[row_mom(P, d)] = -U[row_mom(P, d)];
+}
+
+/* Width of cell position g along axis d (g may lie in a ghost layer).  A   */
+/* ghost cell takes the width of the interior cell whose state it holds     */
+/* (the same index map as the state: wrap, nearest cell, or mirror image);  */
+/* reading: the paper states no ghost widths for non-uniform grids.         */
+static double cell_width(const orc_problem* P, int d, int g) {
+  if (!P->faces[d]) return P->dx[d];
+  int flip = 0;
+  int i = ghost_map(P, d, g, &flip);
+  return P->faces[d][i + 1] - P->faces[d][i];
 }
 
 /* ------------------------------------------------------------------------ */
@@ -328,6 +348,129 @@ double orc_teno5_left(const double* f, double eps, double ct) {
 double orc_teno5_right(const double* f, double eps, double ct) {
   double r[5] = {f[4], f[3], f[2], f[1], f[0]};
   return orc_teno5_left(r, eps, ct);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Fifth-order reconstruction on a non-uniform grid (Sec. 4.2.2), from the   */
+/* Lagrange form the paper prints.  For K cells with faces x_0 < .. < x_K,  */
+/* widths h_j and averages f_j, the primitive P(x_m) = sum_{j<m} h_j f_j is  */
+/* interpolated at the K + 1 faces by the Lagrange basis L_m, and the        */
+/* reconstruction polynomial is its derivative,                              */
+/*   p(x) = sum_m P(x_m) L_m'(x) = sum_j h_j sum_{m>j} L_m'(x) f_j,          */
+/* which is the paper's c_j(x).  Derivatives of L_m are formed from the     */
+/* product rule: the s-th derivative of prod_{i}(x - z_i) is s! times the    */
+/* sum over the ways of dropping s factors of the product of the rest.      */
+/* ------------------------------------------------------------------------ */
+static double prod_deriv(const double* z, int nz, int s, double x) {
+  double total = 0.0;
+  for (int mask = 0; mask < (1 << nz); ++mask) {
+    if (__builtin_popcount(mask) != s) continue;
+    double pr = 1.0;
+    for (int i = 0; i < nz; ++i)
+      if (!((mask >> i) & 1)) pr = pr * (x - z[i]);
+    total = total + pr;
+  }
+  double fact = 1.0;
+  for (int i = 2; i <= s; ++i) fact = fact * i;
+  return total * fact;
+}
+
+/* s-th derivative of the Lagrange basis polynomial L_m on nodes x[0..K]. */
+static double lagrange_deriv(const double* x, int K, int m, int s, double at) {
+  double z[8], den = 1.0;
+  int nz = 0;
+  for (int l = 0; l <= K; ++l) {
+    if (l == m) continue;
+    z[nz++] = x[l];
+    den = den * (x[m] - x[l]);
+  }
+  return prod_deriv(z, nz, s, at) / den;
+}
+
+/* Coefficient of f_j in the l-th derivative of the reconstruction polynomial
+ * of the K cells with faces x[0..K] (l = 0: the value). */
+static double recon_coef(const double* x, int K, int j, int l, double at) {
+  double h = x[j + 1] - x[j], c = 0.0;
+  for (int m = j + 1; m <= K; ++m) c = c + lagrange_deriv(x, K, m, l + 1, at);
+  return h * c;
+}
+
+/* The candidates, smoothness indicators and ideal weights of the fifth-order
+ * reconstruction at the centre cell of five cells with widths h[0..4] and
+ * averages f[0..4] (centre: cell 2).  Stencil r covers cells r..r+2.
+ *   qR[r], qL[r]: candidate r at the right and at the left face of the centre;
+ *   beta[r] = sum_{l=1,2} h_c^(2l-1) int_cell (p_r^(l))^2 dx, the integral by
+ *     two-point Gauss-Legendre quadrature (exact: the integrands are
+ *     polynomials of degree at most two);
+ *   dR[r], dL[r]: ideal weights at the two faces.  Reading (the paper names
+ *     them without a formula for non-uniform grids): the weights for which
+ *     sum_r d_r p_r equals the five-cell reconstruction at that face for all
+ *     data; f_0 enters only stencil 0 and f_4 only stencil 2, so d_0 and d_2
+ *     are those coefficient ratios and d_1 = 1 - d_0 - d_2.  A uniform grid
+ *     gives (0.1, 0.6, 0.3) at the right face and (0.3, 0.6, 0.1) at the left.
+ * f may be NULL (coefficients only: qR, qL and beta are then not formed). */
+void orc_nu_stencil(const double* f, const double* h, double* qR, double* qL, double* beta, double* dR,
+                    double* dL) {
+  double x[6];
+  x[0] = 0.0;
+  for (int j = 0; j < 5; ++j) x[j + 1] = x[j] + h[j];
+  double xl = x[2], xr = x[3], hc = h[2];
+  double g = 0.5 / sqrt(3.0);
+  double gp[2] = {0.5 * (xl + xr) - g * hc, 0.5 * (xl + xr) + g * hc};
+  for (int r = 0; r < 3; ++r) {
+    const double* xs = &x[r];
+    if (f) {
+      double vr = 0.0, vl = 0.0;
+      for (int j = 0; j < 3; ++j) {
+        vr = vr + recon_coef(xs, 3, j, 0, xr) * f[r + j];
+        vl = vl + recon_coef(xs, 3, j, 0, xl) * f[r + j];
+      }
+      qR[r] = vr;
+      qL[r] = vl;
+      double b = 0.0;
+      for (int l = 1; l <= 2; ++l) {
+        double integral = 0.0;
+        for (int k = 0; k < 2; ++k) {
+          double dv = 0.0;
+          for (int j = 0; j < 3; ++j) dv = dv + recon_coef(xs, 3, j, l, gp[k]) * f[r + j];
+          integral = integral + 0.5 * hc * dv * dv;
+        }
+        b = b + pow(hc, 2 * l - 1) * integral;
+      }
+      beta[r] = b;
+    }
+  }
+  double at[2] = {xr, xl};
+  double* dout[2] = {dR, dL};
+  for (int side = 0; side < 2; ++side) {
+    double c5_first = recon_coef(x, 5, 0, 0, at[side]);
+    double c5_last = recon_coef(x, 5, 4, 0, at[side]);
+    double c3_first = recon_coef(&x[0], 3, 0, 0, at[side]);
+    double c3_last = recon_coef(&x[2], 3, 2, 0, at[side]);
+    double d0 = c5_first / c3_first, d2 = c5_last / c3_last;
+    dout[side][0] = d0;
+    dout[side][1] = 1.0 - d0 - d2;
+    dout[side][2] = d2;
+  }
+}
+
+/* WENO5-JS on a non-uniform grid: Jiang-Shu weights d_r/(eps + beta_r)^2 of
+ * the quantities above, normalized, at the right face (fR, the left state of
+ * the face right of the centre) and at the left face (fL). */
+void orc_weno5_nu(const double* f, const double* h, double eps, double* fR, double* fL) {
+  double qR[3], qL[3], beta[3], dR[3], dL[3];
+  orc_nu_stencil(f, h, qR, qL, beta, dR, dL);
+  double numR = 0.0, denR = 0.0, numL = 0.0, denL = 0.0;
+  for (int r = 0; r < 3; ++r) {
+    double aR = dR[r] / sq(eps + beta[r]);
+    double aL = dL[r] / sq(eps + beta[r]);
+    numR = numR + aR * qR[r];
+    denR = denR + aR;
+    numL = numL + aL * qL[r];
+    denL = denL + aL;
+  }
+  *fR = numR / denR;
+  *fL = numL / denL;
 }
 
 /* ------------------------------------------------------------------------ */
@@ -547,13 +690,23 @@ static int face_flux(const orc_problem* P, const double* q, int d, const int idx
     cell_cons_to_prim(P, U, Wc[s]);
   }
   double WL[NEQ_MAX], WR[NEQ_MAX];
+  double hl[5], hr[5];
+  if (P->faces[d])
+    for (int s = 0; s < 5; ++s) {
+      hl[s] = cell_width(P, d, idx[d] - 3 + s);
+      hr[s] = cell_width(P, d, idx[d] - 2 + s);
+    }
   for (int v = 0; v < neq; ++v) {
     double fl[5], fr[5];
     for (int s = 0; s < 5; ++s) {
       fl[s] = Wc[s][v];      /* centre m-1: cells m-3..m+1 */
       fr[s] = Wc[s + 1][v];  /* centre m:   cells m-2..m+2 */
     }
-    if (P->weno_variant == 1) {
+    if (P->faces[d]) {
+      double unused;
+      orc_weno5_nu(fl, hl, P->weno_eps, &WL[v], &unused);
+      orc_weno5_nu(fr, hr, P->weno_eps, &unused, &WR[v]);
+    } else if (P->weno_variant == 1) {
       WL[v] = orc_weno5_z_left(fl, P->weno_eps);
       WR[v] = orc_weno5_z_right(fr, P->weno_eps);
     } else if (P->weno_variant == 2) {
@@ -602,11 +755,11 @@ double orc_kapila_K(const orc_problem* P, const double* W) {
  *   D_v = (F_{m-1/2} - F_{m+1/2}) / dx_d for every row,
  *   plus alpha_cell (u_{m+1/2} - u_{m-1/2}) / dx_d on the alpha rows, where
  *   alpha_cell is the cell-average volume fraction. */
-static void axis_contribution(const orc_problem* P, int d, const double* Flo, double ulo,
+static void axis_contribution(const orc_problem* P, int d, int i_d, const double* Flo, double ulo,
                               const double* Fhi, double uhi, const double* Ucell,
                               double* Dv) {
   int nf = P->num_fluids, neq = orc_num_eqs(P);
-  double inv_dx = 1.0 / P->dx[d];
+  double inv_dx = 1.0 / cell_width(P, d, i_d);
   for (int v = 0; v < neq; ++v) Dv[v] = inv_dx * (Flo[v] - Fhi[v]);
   if (nf == 2) {
     double K[2] = {0.0, 0.0};
@@ -657,7 +810,7 @@ int orc_rhs(const orc_problem* P, const double* q, double* rhs) {
         int64_t c = ((int64_t)id[2] * P->n[1] + id[1]) * P->n[0] + id[0];
         double Uc[NEQ_MAX], Dv[NEQ_MAX];
         for (int v = 0; v < neq; ++v) Uc[v] = q[v * nc + c];
-        axis_contribution(P, d, &Fl[(size_t)m * NEQ_MAX], ul[m], &Fl[(size_t)(m + 1) * NEQ_MAX],
+        axis_contribution(P, d, m, &Fl[(size_t)m * NEQ_MAX], ul[m], &Fl[(size_t)(m + 1) * NEQ_MAX],
                           ul[m + 1], Uc, Dv);
         for (int v = 0; v < neq; ++v) rhs[v * nc + c] = rhs[v * nc + c] + Dv[v];
       }
@@ -692,7 +845,7 @@ int orc_rhs_cells(const orc_problem* P, const double* q, int64_t ncells, const i
       bad |= face_flux(P, q, d, id, Flo, &ulo);
       id[d] = idx[d] + 1;
       bad |= face_flux(P, q, d, id, Fhi, &uhi);
-      axis_contribution(P, d, Flo, ulo, Fhi, uhi, Uc, Dv);
+      axis_contribution(P, d, idx[d], Flo, ulo, Fhi, uhi, Uc, Dv);
       for (int v = 0; v < neq; ++v) acc[v] = acc[v] + Dv[v];
     }
     for (int v = 0; v < neq; ++v) out[s * neq + v] = acc[v];
@@ -723,8 +876,10 @@ int orc_max_signal(const orc_problem* P, const double* q, double* smax_out) {
     double c2 = sound_speed_sq(rho, W[row_E(P)], Gam, Pi);
     if (!(c2 > 0.0) || !isfinite(c2)) bad = 1;
     double cs = sqrt(c2);
+    int idx[3] = {(int)(c % P->n[0]), (int)((c / P->n[0]) % P->n[1]),
+                  (int)(c / ((int64_t)P->n[0] * P->n[1]))};
     double s = 0.0;
-    for (int d = 0; d < P->ndim; ++d) s = s + (fabs(W[row_mom(P, d)]) + cs) * (1.0 / P->dx[d]);
+    for (int d = 0; d < P->ndim; ++d) s = s + (fabs(W[row_mom(P, d)]) + cs) * (1.0 / cell_width(P, d, idx[d]));
     if (!isfinite(s)) bad = 1;
     if (s > smax) smax = s;
   }
@@ -843,12 +998,25 @@ int orc_conserved_sums(const orc_problem* P, const double* q, double* sums) {
   if (orc_validate(P)) return ORC_ERR_ARG;
   int neq = orc_num_eqs(P);
   int64_t nc = ncell(P);
+  int uniform = !P->faces[0] && !P->faces[1] && !P->faces[2];
   double vol = 1.0;
   for (int d = 0; d < P->ndim; ++d) vol = vol * P->dx[d];
   for (int v = 0; v < neq; ++v) {
     long double acc = 0.0L;
-    for (int64_t c = 0; c < nc; ++c) acc += (long double)q[v * nc + c];
-    sums[v] = (double)acc * vol;
+    if (uniform) {
+      for (int64_t c = 0; c < nc; ++c) acc += (long double)q[v * nc + c];
+      sums[v] = (double)acc * vol;
+    } else {
+      /* non-uniform grid: each cell's own volume */
+      for (int64_t c = 0; c < nc; ++c) {
+        int idx[3] = {(int)(c % P->n[0]), (int)((c / P->n[0]) % P->n[1]),
+                      (int)(c / ((int64_t)P->n[0] * P->n[1]))};
+        long double cv = 1.0L;
+        for (int d = 0; d < P->ndim; ++d) cv *= (long double)cell_width(P, d, idx[d]);
+        acc += (long double)q[v * nc + c] * cv;
+      }
+      sums[v] = (double)acc;
+    }
   }
   return ORC_OK;
 }

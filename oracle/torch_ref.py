@@ -42,7 +42,9 @@ def sqrt(x):
 
 class Problem:
     def __init__(self, ndim, n, num_fluids, dx, gamma, pi_inf, bc_lo, bc_hi, weno_eps=1e-6, weno_variant=0,
-                 riemann=0, low_mach=0, model=0):
+                 riemann=0, low_mach=0, model=0, faces=None):
+        if faces is not None and any(f is not None for f in faces):
+            raise NotImplementedError("the torch reference covers uniform grids only")
         self.ndim = ndim
         self.n = tuple(n) + (1,) * (3 - len(n))
         self.nf = num_fluids

@@ -59,6 +59,7 @@ class Case:
     riemann: int = 0        # 0: HLLC, 1: HLL
     low_mach: int = 0       # 0: none, 1: Thornber et al. velocity correction, 2: Chen et al. APC
     model: int = 0          # 0: Allaire (K = 0), 1: Kapila (K div u on the alpha rows)
+    faces: tuple = None     # per axis None (uniform dx) or the n + 1 face coordinates
     extra: dict = field(default_factory=dict)
 
     @property
@@ -70,12 +71,16 @@ class Case:
         return int(self.n[0]) * int(self.n[1]) * int(self.n[2])
 
     def problem_kwargs(self) -> dict:
-        """Plain numbers describing the problem (shared by both sides)."""
-        return dict(ndim=self.ndim, n=tuple(self.n), num_fluids=self.num_fluids,
-                    dx=tuple(self.dx), gamma=tuple(self.gamma),
-                    pi_inf=tuple(self.pi_inf), bc_lo=tuple(self.bc_lo),
-                    bc_hi=tuple(self.bc_hi), weno_eps=self.weno_eps, weno_variant=self.weno_variant,
-                    riemann=self.riemann, low_mach=self.low_mach, model=self.model)
+        """Plain numbers describing the problem (shared by both sides); the
+        face coordinates only for a non-uniform grid."""
+        kw = dict(ndim=self.ndim, n=tuple(self.n), num_fluids=self.num_fluids,
+                  dx=tuple(self.dx), gamma=tuple(self.gamma),
+                  pi_inf=tuple(self.pi_inf), bc_lo=tuple(self.bc_lo),
+                  bc_hi=tuple(self.bc_hi), weno_eps=self.weno_eps, weno_variant=self.weno_variant,
+                  riemann=self.riemann, low_mach=self.low_mach, model=self.model)
+        if self.faces is not None:
+            kw["faces"] = self.faces
+        return kw
 
 
 def _pad3(t, fill):
@@ -142,7 +147,25 @@ def sod(n: int = 200, t_end: float = 0.2, cfl: float = 0.5) -> Case:
 # ----------------------------------------------------------------------------
 # Smooth two-component advection (Sec. 3.5 convergence problem)
 # ----------------------------------------------------------------------------
-def advection_1d(n: int, amplitude: float = 1.0, gamma2: float = 1.4) -> Case:
+def stretched_faces(n: int, L: float = 1.0, a: float = 0.0) -> np.ndarray:
+    """n + 1 face coordinates of a smoothly stretched grid on [0, L]:
+    x(xi) = L (xi - a sin(2 pi xi) / (2 pi)) at xi = i/n.  The widths follow
+    dx/dxi = L (1 - a cos(2 pi xi)), periodic in xi; |a| < 1, and the largest
+    to smallest width ratio is (1 + |a|)/(1 - |a|).  a > 0 clusters cells at
+    both ends, a < 0 at the centre; a = 0 is the uniform grid."""
+    xi = np.arange(n + 1, dtype=np.float64) / n
+    x = L * (xi - a * np.sin(2 * np.pi * xi) / (2 * np.pi))
+    x[0], x[-1] = 0.0, L
+    return x
+
+
+def _sin_averages(faces, shift=0.0):
+    a = faces[:-1] - shift
+    b = faces[1:] - shift
+    return (np.cos(2 * np.pi * a) - np.cos(2 * np.pi * b)) / (2 * np.pi * (faces[1:] - faces[:-1]))
+
+
+def advection_1d(n: int, amplitude: float = 1.0, gamma2: float = 1.4, stretch: float = 0.0) -> Case:
     """alpha_i = alpha_i rho_i = 0.5 + (-1)^i A sin(2 pi x), u = p = 1, periodic.
 
     Cell averages of sin(2 pi x) over [a, b] are
@@ -150,27 +173,25 @@ def advection_1d(n: int, amplitude: float = 1.0, gamma2: float = 1.4) -> Case:
     ideal with gamma = 1.4 this is the problem as printed (volume fractions
     leave [0, 1] but the mixture stays an ideal gas with Gamma = 2.5, so it is
     pure linear advection); A = 0.25 with gamma2 = 1.6 is a physical variant.
+    stretch != 0 puts the problem on the stretched grid of stretched_faces(n,
+    1, stretch) (cell averages over the stretched cells).
     """
     dx = 1.0 / n
-    a = np.arange(n, dtype=np.float64) * dx
-    b = a + dx
-    s = (np.cos(2 * np.pi * a) - np.cos(2 * np.pi * b)) / (2 * np.pi * dx)
+    faces = stretched_faces(n, 1.0, stretch)
+    s = _sin_averages(faces)
     a1 = 0.5 - amplitude * s
     a2 = 0.5 + amplitude * s
     ones = np.ones(n)
     w = np.stack([a1, a2, ones, ones, a1, a2]).reshape(6, 1, 1, n).astype(np.float64)
     return Case(f"advection_{n}", 1, (n, 1, 1), 2, (dx, 1.0, 1.0), (1.4, gamma2), (0.0, 0.0),
                 (PERIODIC,) * 3, (PERIODIC,) * 3, w, cfl=0.5,
+                faces=(faces, None, None) if stretch != 0.0 else None,
                 extra=dict(amplitude=amplitude))
 
 
-def advection_exact_average(n: int, amplitude: float, t: float, u: float = 1.0):
+def advection_exact_average(n: int, amplitude: float, t: float, u: float = 1.0, stretch: float = 0.0):
     """Exact cell averages of alpha_1 after advection by u*t (periodic)."""
-    dx = 1.0 / n
-    a = np.arange(n, dtype=np.float64) * dx - u * t
-    b = a + dx
-    s = (np.cos(2 * np.pi * a) - np.cos(2 * np.pi * b)) / (2 * np.pi * dx)
-    return 0.5 - amplitude * s
+    return 0.5 - amplitude * _sin_averages(stretched_faces(n, 1.0, stretch), u * t)
 
 
 # ----------------------------------------------------------------------------
