@@ -2,16 +2,18 @@
  * mfc355.h -- C ABI of the MI355X (gfx950) five-equation right-hand side.
  *
  * The library evaluates the semi-discrete right-hand side of the
- * five-equation diffuse-interface model in Allaire form (arXiv 2503.07953,
- * Sec. 2.1.1, eq. five_eqn_transport with K = 0) closed by the stiffened-gas
- * equation of state (Sec. 2.2, eq. eos), on a uniform structured grid, and
+ * five-equation diffuse-interface model (arXiv 2503.07953, Sec. 2.1.1, eq.
+ * five_eqn_transport; Allaire form with K = 0 by default, Kapila's K as an
+ * option) closed by the stiffened-gas equation of state (Sec. 2.2, eq. eos),
+ * on a structured grid (uniform, or non-uniform per axis, Sec. 4.2.2), and
  * advances it with the three-stage SSP Runge-Kutta scheme (Sec. 3.4):
  *
  *   dq_{ijk}/dt = sum_d (F_{-1/2} - F_{+1/2})/dx_d + alpha (div u)_{ijk}
  *
  * (eq. eqn:rhs with s = 0 and h = -alpha), with face fluxes from WENO5-JS
  * reconstruction of primitive variables (Sec. 3.2.1) and the HLLC solver
- * (Sec. 3.2.2), which also returns the face velocity used for div u.
+ * (Sec. 3.2.2), which also returns the face velocity used for div u; other
+ * reconstruction weights, face solvers and low-Mach treatments are options.
  *
  * Conventions for every entry point
  * ---------------------------------
@@ -46,7 +48,7 @@
 extern "C" {
 #endif
 
-#define MFC_ABI_VERSION 4
+#define MFC_ABI_VERSION 5
 
 enum {
   MFC_OK = 0,
@@ -95,13 +97,30 @@ enum { MFC_WENO_JS = 0, MFC_WENO_Z = 1, MFC_TENO = 2, MFC_WENO_M = 3 };
  *             (the paper prints no HLL formula: these are the readings). */
 enum { MFC_HLLC = 0, MFC_HLL = 1 };
 
-/* Low-Mach treatment (the paper's low-Mach section):
+/* Low-Mach treatment (the paper's low-Mach section, Sec. 4.2.4), with
+ * z = min(max(|u_L|/c_L, |u_R|/c_R), 1) from the face states as reconstructed:
  *   MFC_LOW_MACH_NONE      the face states as reconstructed;
- *   MFC_LOW_MACH_THORNBER  Thornber et al.: with z = min(max(|u_L|/c_L,
- *                          |u_R|/c_R), 1) the face-normal velocities become
+ *   MFC_LOW_MACH_THORNBER  Thornber et al.: the face-normal velocities become
  *                          (u_L + u_R)/2 +- z (u_L - u_R)/2 before the face
- *                          solver (either one); c of the uncorrected states. */
-enum { MFC_LOW_MACH_NONE = 0, MFC_LOW_MACH_THORNBER = 1 };
+ *                          solver (either one);
+ *   MFC_LOW_MACH_CHEN_APC  Chen et al.: the anti-dissipation pressure
+ *                          correction (z - 1) p_d on the normal-momentum flux
+ *                          and (z - 1) p_d S* on the energy flux of both HLLC
+ *                          star regions, p_d = rho_L rho_R (S_L - u_L)
+ *                          (S_R - u_R)(u_R - u_L) / (rho_R (S_R - u_R) -
+ *                          rho_L (S_L - u_L)); HLLC only. */
+enum { MFC_LOW_MACH_NONE = 0, MFC_LOW_MACH_THORNBER = 1, MFC_LOW_MACH_CHEN_APC = 2 };
+
+/* Five-equation model (Sec. 2.1.1):
+ *   MFC_MODEL_ALLAIRE  K = 0: the alpha_i rows carry alpha_i div u;
+ *   MFC_MODEL_KAPILA   the alpha_1 row carries (alpha_1 + K) div u and the
+ *                      alpha_2 row (alpha_2 - K) div u, K = (rho_2 c_2^2 -
+ *                      rho_1 c_1^2) / (rho_1 c_1^2/alpha_1 + rho_2 c_2^2/alpha_2),
+ *                      phasic c_i^2 = gamma_i (p + pi_inf,i)/rho_i, from each
+ *                      cell's average state.  The paper prints a plus sign in
+ *                      the numerator; the difference is read, since only it
+ *                      vanishes for two identical fluids.  Two fluids only. */
+enum { MFC_MODEL_ALLAIRE = 0, MFC_MODEL_KAPILA = 1 };
 
 typedef struct {
   int32_t abi_version; /* must equal MFC_ABI_VERSION */
@@ -121,7 +140,8 @@ typedef struct {
                           a product of eight terms of size >= 4 eps */
   int32_t weno_variant; /* MFC_WENO_JS, MFC_WENO_Z, MFC_TENO or MFC_WENO_M */
   int32_t riemann_solver; /* MFC_HLLC (0) or MFC_HLL */
-  int32_t low_mach;       /* MFC_LOW_MACH_NONE (0) or MFC_LOW_MACH_THORNBER */
+  int32_t low_mach;       /* MFC_LOW_MACH_NONE (0), _THORNBER or _CHEN_APC (HLLC only) */
+  int32_t model;          /* MFC_MODEL_ALLAIRE (0) or MFC_MODEL_KAPILA (two fluids) */
 } mfc_problem;
 
 typedef struct mfc_ctx mfc_ctx;
@@ -167,7 +187,29 @@ int mfc_max_signal(mfc_ctx* ctx, const void* q, double* smax_dev, void* hip_stre
 int mfc_step(mfc_ctx* ctx, void* q, double cfl, double dt_fixed, double t_remaining,
              double* dt_dev, void* hip_stream);
 
-/* Conservation diagnostics: sums_dev[v] = (sum over cells of q[v]) * cell volume,
+/* Non-uniform grid along `axis` (Sec. 4.2.2): faces is a HOST array of the
+ * n[axis] + 1 cell-face coordinates x_{-1/2} .. x_{n-1/2}, strictly
+ * increasing and finite (read during the call, not kept); NULL restores the
+ * uniform spacing dx[axis].  Cell i then has width h_i = x_{i+1/2} -
+ * x_{i-1/2}, which replaces dx in the flux difference, the alpha source, the
+ * signal speed and the conservation sums (cell volume h_x h_y h_z).  The
+ * fifth-order reconstruction on the grid: in the unit coordinate of each
+ * centre cell, candidate r is the quadratic with the stencil's data as its
+ * cell averages, its smoothness indicator is sum_{l=1,2} h^(2l-1)
+ * int_cell (d^l p/dx^l)^2 dx, and the ideal weights at each face are those
+ * that combine the candidates into the quartic with the five cells' averages
+ * (the paper states the candidates and indicators; these weights are the
+ * reading).  Ghost cells take the width of the cell whose state they hold
+ * (wrap, nearest cell or mirror image).  The coefficients are formed on the
+ * host in double and kept on the device in the context (allocated at the
+ * first call, synchronous copy).
+ * WENO5-JS problems only (MFC_ERR_UNSUPPORTED otherwise); while any axis is
+ * non-uniform the RHS and step adjoints return MFC_ERR_UNSUPPORTED, and
+ * mfc_step_static (no context) always uses the uniform spacing.
+ * MFC_ERR_ARG for a bad axis or face array. */
+int mfc_set_grid(mfc_ctx* ctx, int axis, const double* faces);
+
+/* Conservation diagnostics: sums_dev[v] =(sum over cells of q[v]) * cell volume,
  * neq device doubles, accumulated in double with a fixed reduction order. */
 int mfc_conserved_sums(mfc_ctx* ctx, const void* q, double* sums_dev, void* hip_stream);
 

@@ -13,10 +13,11 @@ import os
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libmfc355.so")
 
-MFC_ABI_VERSION = 4
+MFC_ABI_VERSION = 5
 MFC_WENO_JS, MFC_WENO_Z, MFC_TENO, MFC_WENO_M = 0, 1, 2, 3
 MFC_HLLC, MFC_HLL = 0, 1
-MFC_LOW_MACH_NONE, MFC_LOW_MACH_THORNBER = 0, 1
+MFC_LOW_MACH_NONE, MFC_LOW_MACH_THORNBER, MFC_LOW_MACH_CHEN_APC = 0, 1, 2
+MFC_MODEL_ALLAIRE, MFC_MODEL_KAPILA = 0, 1
 MFC_OK, MFC_ERR_ARG, MFC_ERR_SHAPE, MFC_ERR_UNSUPPORTED = 0, -1, -2, -3
 MFC_ERR_HIP, MFC_ERR_NONFINITE, MFC_ERR_ALLOC = -4, -5, -6
 MFC_BC_PERIODIC, MFC_BC_EXTRAP, MFC_BC_SLIPWALL = 0, 1, 2
@@ -39,6 +40,7 @@ class mfc_problem(ctypes.Structure):
         ("weno_variant", ctypes.c_int32),
         ("riemann_solver", ctypes.c_int32),
         ("low_mach", ctypes.c_int32),
+        ("model", ctypes.c_int32),
     ]
 
 
@@ -62,6 +64,7 @@ SIGNATURES = {
     "mfc_max_signal": (_I, [_V, _V, _V, _V]),
     "mfc_step": (_I, [_V, _V, _D, _D, _D, _V, _V]),
     "mfc_conserved_sums": (_I, [_V, _V, _V, _V]),
+    "mfc_set_grid": (_I, [_V, _I, _V]),
     "mfc_check": (_I, [_V, _V]),
     "mfc_set_timing": (_I, [_V, _I]),
     "mfc_get_timing": (_I, [_V, _V, _V]),
@@ -119,7 +122,7 @@ class MfcError(RuntimeError):
 
 def make_problem(ndim, n, num_fluids, dx, gamma, pi_inf, bc_lo, bc_hi, weno_eps=1e-6,
                  precision=MFC_FP64, weno_variant=MFC_WENO_JS, riemann=MFC_HLLC,
-                 low_mach=MFC_LOW_MACH_NONE) -> mfc_problem:
+                 low_mach=MFC_LOW_MACH_NONE, model=MFC_MODEL_ALLAIRE) -> mfc_problem:
     p = mfc_problem()
     p.abi_version = MFC_ABI_VERSION
     p.ndim = int(ndim)
@@ -138,4 +141,5 @@ def make_problem(ndim, n, num_fluids, dx, gamma, pi_inf, bc_lo, bc_hi, weno_eps=
     p.weno_variant = int(weno_variant)
     p.riemann_solver = int(riemann)
     p.low_mach = int(low_mach)
+    p.model = int(model)
     return p

@@ -381,7 +381,7 @@ __host__ __device__ __forceinline__ void side_scalars_vjp(const Params& pm, cons
   }
 }
 
-template <int NF, int D, int DIR>
+template <int NF, int D, int DIR, bool APC = false>
 __host__ __device__ __forceinline__ void hllc_vjp(const Params& pm, const double* WL, const double* WR,
                                                   const double* Fb, double ufb, double* WLb, double* WRb,
                                                   double* uf_out = nullptr) {
@@ -518,10 +518,53 @@ __host__ __device__ __forceinline__ void hllc_vjp(const Params& pm, const double
     }
   }
 
-  // wave speeds: S* = num/den, S_L / S_R from the Davis estimates
+  // APC term of Chen et al. in the star region: A = (z - 1) p_d on the normal
+  // momentum and A S* on the energy, p_d = P / den2 with P = rho_L rho_R a_L
+  // a_R (u_R - u_L), den2 = rho_R a_R - rho_L a_L (= 1/rnd); z = |u|/c of the
+  // side the max took (ties: left), no derivative when clipped at 1
   double rhoLb = 0.0, unLb = 0.0, pLb = 0.0, cLb = 0.0;
   double rhoRb = 0.0, unRb = 0.0, pRb = 0.0, cRb = 0.0;
   double SLb = 0.0, SRb = 0.0;
+  if constexpr (APC) {
+    if (star) {
+      const double mL = fabs(L.un) * fast_rcp(L.c), mR = fabs(Rs.un) * fast_rcp(Rs.c);
+      const bool zleft = mL >= mR;
+      const double zm = zleft ? mL : mR;
+      const bool clipped = zm > 1.0;
+      const double z = clipped ? 1.0 : zm;
+      const double du = Rs.un - L.un;
+      const double rr = L.rho * Rs.rho;
+      const double pd = rr * aL * aR * du * rnd;
+      const double Ab = Fb[R::MOM + DIR] + Fb[R::E] * Sstar;
+      Sstarb += Fb[R::E] * ((z - 1.0) * pd);
+      const double zb = Ab * pd;
+      const double pdb = Ab * (z - 1.0);
+      const double Pb = pdb * rnd;
+      const double den2b = -pdb * pd * rnd;
+      rhoLb += Pb * Rs.rho * aL * aR * du - den2b * aL;
+      rhoRb += Pb * L.rho * aL * aR * du + den2b * aR;
+      const double aLb = Pb * rr * aR * du - den2b * L.rho;
+      const double aRb = Pb * rr * aL * du + den2b * Rs.rho;
+      const double dub = Pb * rr * aL * aR;
+      unRb += dub - aRb;
+      unLb -= dub + aLb;
+      SLb += aLb;
+      SRb += aRb;
+      if (!clipped) {
+        if (zleft) {
+          const double rc = fast_rcp(L.c);
+          unLb += zb * ((L.un > 0.0) ? rc : ((L.un < 0.0) ? -rc : 0.0));
+          cLb -= zb * fabs(L.un) * rc * rc;
+        } else {
+          const double rc = fast_rcp(Rs.c);
+          unRb += zb * ((Rs.un > 0.0) ? rc : ((Rs.un < 0.0) ? -rc : 0.0));
+          cRb -= zb * fabs(Rs.un) * rc * rc;
+        }
+      }
+    }
+  }
+
+  // wave speeds: S* = num/den, S_L / S_R from the Davis estimates
   if (star) {
     if (useL)
       SLb += SKb;
@@ -752,15 +795,33 @@ __host__ __device__ __forceinline__ void thornber_vjp(const Params& pm, const do
   }
 }
 
-// The face-solver adjoint of a kernel instantiation: RS = 0 HLLC, 1 HLL.
+// The face-solver adjoint of a kernel instantiation (option bits RS as for
+// riemann()): HLL, or HLLC with or without the APC term.
 template <int RS, int NF, int D, int DIR>
 __host__ __device__ __forceinline__ void riemann_vjp(const Params& pm, const double* WL, const double* WR,
                                                      const double* Fb, double ufb, double* WLb, double* WRb,
                                                      double* uf_out = nullptr) {
-  if constexpr (RS == 1)
+  if constexpr ((RS & RS_HLL) != 0)
     hll_vjp<NF, D, DIR>(pm, WL, WR, Fb, ufb, WLb, WRb, uf_out);
   else
-    hllc_vjp<NF, D, DIR>(pm, WL, WR, Fb, ufb, WLb, WRb, uf_out);
+    hllc_vjp<NF, D, DIR, (RS & RS_APC) != 0>(pm, WL, WR, Fb, ufb, WLb, WRb, uf_out);
+}
+
+// Gradient of Kapila's K (kapila_K) with respect to the cell's p, alpha_1 and
+// alpha_2.  With z_i = gamma_i (p + pi_inf,i), N = z_2 - z_1, Q = z_1 alpha_2 +
+// z_2 alpha_1 and K = N alpha_1 alpha_2 / Q:
+//   dK/dp = ((gamma_2 - gamma_1) alpha_1 alpha_2 - K (gamma_1 alpha_2 + gamma_2 alpha_1)) / Q,
+//   dK/dalpha_1 = (N alpha_2 - K z_2) / Q,  dK/dalpha_2 = (N alpha_1 - K z_1) / Q.
+__host__ __device__ __forceinline__ void kapila_K_grad(const Params& pm, double p, double a1, double a2, double& dp,
+                                                       double& da1, double& da2) {
+  const double z1 = pm.gam[0] * (p + pm.pinf[0]);
+  const double z2 = pm.gam[1] * (p + pm.pinf[1]);
+  const double N = z2 - z1;
+  const double rQ = fast_rcp(z1 * a2 + z2 * a1);
+  const double K = N * (a1 * a2) * rQ;
+  dp = ((pm.gam[1] - pm.gam[0]) * (a1 * a2) - K * (pm.gam[0] * a2 + pm.gam[1] * a1)) * rQ;
+  da1 = (N * a2 - K * z2) * rQ;
+  da2 = (N * a1 - K * z1) * rQ;
 }
 
 }  // namespace mfc

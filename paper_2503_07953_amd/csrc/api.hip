@@ -6,6 +6,9 @@
 #include <stdlib.h>
 #include <string.h>
 
+#include <cmath>
+#include <mutex>
+#include <utility>
 #include <string>
 #include <vector>
 
@@ -95,6 +98,11 @@ struct mfc_ctx {
   double* vbuf;       // L^T v
   double* b1;         // stage cotangents
   double* b2;
+  // non-uniform grid (mfc_set_grid): face coordinates per axis (empty:
+  // uniform spacing dx) and the device coefficient tables of every active axis
+  std::vector<double> faces[3];
+  double* nu_d[3];
+  float* nu_f[3];
 };
 
 namespace {
@@ -162,6 +170,128 @@ int ensure_vjp_scratch(mfc_ctx* c) {
   return MFC_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Non-uniform grids (Sec. 4.2.2): reconstruction tables built on the host.
+// For the centre cell at position c of an axis, with unit coordinate
+// xi = (x - x_c)/h_c, candidate r (cells c - 2 + r .. c + r) is the quadratic
+// m0 + m1 xi + m2 xi^2 with the data as its cell averages: m = A^-1 f, A the
+// 3 x 3 matrix of cell averages of 1, xi, xi^2 over the stencil's cells.  The
+// ideal weights at a face are the least-squares (here exact) solution of
+// sum_r d_r v_r = v5, v_r the candidate's value functional at the face and v5
+// that of the quartic with the five cells' averages.  Ghost cells take the
+// width of the cell whose state they hold (ghost_index).
+// ---------------------------------------------------------------------------
+namespace {
+
+// Solve the n x n system M X = B for X (k right-hand sides), Gaussian
+// elimination with partial pivoting; M and B are overwritten.  False if singular.
+bool solve_dense(int n, int k, double* M, double* B) {
+  for (int col = 0; col < n; ++col) {
+    int piv = col;
+    for (int r = col + 1; r < n; ++r)
+      if (fabs(M[r * n + col]) > fabs(M[piv * n + col])) piv = r;
+    if (!(fabs(M[piv * n + col]) > 0.0)) return false;
+    if (piv != col) {
+      for (int j = 0; j < n; ++j) std::swap(M[col * n + j], M[piv * n + j]);
+      for (int j = 0; j < k; ++j) std::swap(B[col * k + j], B[piv * k + j]);
+    }
+    for (int r = col + 1; r < n; ++r) {
+      const double f = M[r * n + col] / M[col * n + col];
+      for (int j = col; j < n; ++j) M[r * n + j] -= f * M[col * n + j];
+      for (int j = 0; j < k; ++j) B[r * k + j] -= f * B[col * k + j];
+    }
+  }
+  for (int col = n - 1; col >= 0; --col) {
+    for (int j = 0; j < k; ++j) {
+      double v = B[col * k + j];
+      for (int c2 = col + 1; c2 < n; ++c2) v -= M[col * n + c2] * B[c2 * k + j];
+      B[col * k + j] = v / M[col * n + col];
+    }
+  }
+  return true;
+}
+
+// Inverse of the moment matrix of `deg + 1` cells with unit-coordinate faces
+// e[0..deg+1]: row k of the result maps the cell averages to m_k.
+bool moment_inverse(int deg, const double* e, double* inv) {
+  const int n = deg + 1;
+  double M[25], B[25];
+  for (int j = 0; j < n; ++j)
+    for (int k = 0; k < n; ++k) {
+      const double a = e[j], b = e[j + 1];
+      M[j * n + k] = (std::pow(b, k + 1) - std::pow(a, k + 1)) / ((k + 1) * (b - a));
+      B[j * n + k] = (j == k) ? 1.0 : 0.0;
+    }
+  // M X = I gives X = M^-1 with X[k][j] the weight of average j in m_k
+  if (!solve_dense(n, n, M, B)) return false;
+  for (int i = 0; i < n * n; ++i) inv[i] = B[i];
+  return true;
+}
+
+// Table of one axis: kNuCoefs rows of n + 6 entries (positions -3 .. n + 2).
+bool build_axis_table(const mfc::Params& pm, int d, const std::vector<double>& faces, double dx,
+                      std::vector<double>& tab) {
+  const int n = pm.n[d];
+  const long long st = n + 6;
+  tab.assign((size_t)mfc::kNuCoefs * st, 0.0);
+  auto width = [&](int pos) {
+    if (faces.empty()) return dx;
+    bool flip;
+    const int i = mfc::ghost_index(pos, n, pm.bc_lo[d], pm.bc_hi[d], flip);
+    return faces[i + 1] - faces[i];
+  };
+  for (int pos = -3; pos <= n + 2; ++pos) tab[mfc::NU_INVW * st + pos + 3] = 1.0 / width(pos);
+  for (int pos = -1; pos <= n; ++pos) {
+    const double hc = width(pos);
+    double e[6];
+    e[2] = -0.5;
+    e[3] = 0.5;
+    e[1] = e[2] - width(pos - 1) / hc;
+    e[0] = e[1] - width(pos - 2) / hc;
+    e[4] = e[3] + width(pos + 1) / hc;
+    e[5] = e[4] + width(pos + 2) / hc;
+    double inv3[3][9];
+    for (int r = 0; r < 3; ++r) {
+      if (!moment_inverse(2, &e[r], inv3[r])) return false;
+      // m_k = sum_j inv[k][j] f_{r+j}; m0 - f_2 subtracts the centre (j = 2 - r)
+      for (int k = 0; k < 3; ++k) {
+        double w[3] = {inv3[r][k * 3 + 0], inv3[r][k * 3 + 1], inv3[r][k * 3 + 2]};
+        if (k == 0) w[2 - r] -= 1.0;
+        // zero-sum w: w . f = -w_0 (f_1 - f_0) + w_2 (f_2 - f_1) over the stencil
+        const int row = (k == 0 ? mfc::NU_MU0 : k == 1 ? mfc::NU_M1 : mfc::NU_M2) + 2 * r;
+        tab[row * st + pos + 3] = -w[0];
+        tab[(row + 1) * st + pos + 3] = w[2];
+      }
+    }
+    double inv5[25];
+    if (!moment_inverse(4, e, inv5)) return false;
+    for (int side = 0; side < 2; ++side) {
+      const double xi = side == 0 ? 0.5 : -0.5;
+      double v5[5] = {0, 0, 0, 0, 0}, V[3][5] = {};
+      for (int j = 0; j < 5; ++j)
+        for (int k = 0; k < 5; ++k) v5[j] += std::pow(xi, k) * inv5[k * 5 + j];
+      for (int r = 0; r < 3; ++r)
+        for (int j = 0; j < 3; ++j)
+          for (int k = 0; k < 3; ++k) V[r][r + j] += std::pow(xi, k) * inv3[r][k * 3 + j];
+      double N[9], rhs[3];
+      for (int a = 0; a < 3; ++a) {
+        rhs[a] = 0.0;
+        for (int j = 0; j < 5; ++j) rhs[a] += V[a][j] * v5[j];
+        for (int b = 0; b < 3; ++b) {
+          N[a * 3 + b] = 0.0;
+          for (int j = 0; j < 5; ++j) N[a * 3 + b] += V[a][j] * V[b][j];
+        }
+      }
+      if (!solve_dense(3, 1, N, rhs)) return false;
+      const int row = side == 0 ? mfc::NU_DR : mfc::NU_DL;
+      for (int r = 0; r < 3; ++r) tab[(row + r) * st + pos + 3] = rhs[r];
+    }
+  }
+  return true;
+}
+
+}  // namespace
+
 // Smallest accepted WENO eps: (4 eps)^8 stays far above the smallest normal
 // double (2.2e-308) for every eps >= 1e-30.
 constexpr double kMinWenoEps = 1e-30;
@@ -203,10 +333,16 @@ mfc::Params make_params(const mfc_problem& p) {
     pm.G[i] = 1.0 / (p.gamma[k] - 1.0);
     pm.P[i] = p.gamma[k] * p.pi_inf[k] / (p.gamma[k] - 1.0);
   }
+  for (int i = 0; i < 2; ++i) {
+    const int k = (i < p.num_fluids) ? i : 0;
+    pm.gam[i] = p.gamma[k];
+    pm.pinf[i] = p.pi_inf[k];
+  }
   pm.eps = p.weno_eps;
   pm.weno_variant = p.weno_variant;
   pm.riemann = p.riemann_solver;
   pm.low_mach = p.low_mach;
+  pm.model = p.model;
   pm.ncell = (long long)p.n[0] * p.n[1] * p.n[2];
   return pm;
 }
@@ -269,7 +405,13 @@ int mfc_validate(const mfc_problem* p) {
   if (!(p->weno_eps >= kMinWenoEps) || !(p->weno_eps < 1e300)) return MFC_ERR_ARG;
   if (p->weno_variant < MFC_WENO_JS || p->weno_variant > MFC_WENO_M) return MFC_ERR_UNSUPPORTED;
   if (p->riemann_solver != MFC_HLLC && p->riemann_solver != MFC_HLL) return MFC_ERR_UNSUPPORTED;
-  if (p->low_mach != MFC_LOW_MACH_NONE && p->low_mach != MFC_LOW_MACH_THORNBER) return MFC_ERR_UNSUPPORTED;
+  if (p->low_mach != MFC_LOW_MACH_NONE && p->low_mach != MFC_LOW_MACH_THORNBER && p->low_mach != MFC_LOW_MACH_CHEN_APC)
+    return MFC_ERR_UNSUPPORTED;
+  // the APC term corrects the HLLC star fluxes; HLL has no star region
+  if (p->low_mach == MFC_LOW_MACH_CHEN_APC && p->riemann_solver != MFC_HLLC) return MFC_ERR_UNSUPPORTED;
+  if (p->model != MFC_MODEL_ALLAIRE && p->model != MFC_MODEL_KAPILA) return MFC_ERR_UNSUPPORTED;
+  // K couples the two phases' volume fractions
+  if (p->model == MFC_MODEL_KAPILA && p->num_fluids != 2) return MFC_ERR_UNSUPPORTED;
   return MFC_OK;
 }
 
@@ -298,6 +440,10 @@ int mfc_create(const mfc_problem* p, mfc_ctx** out) {
   c->timer = nullptr;
   c->vjp = mfc::VjpScratch{{nullptr, nullptr, nullptr}, {nullptr, nullptr, nullptr}, false};
   c->vbuf = c->b1 = c->b2 = nullptr;
+  for (int d = 0; d < 3; ++d) {
+    c->nu_d[d] = nullptr;
+    c->nu_f[d] = nullptr;
+  }
   if (hipGetDevice(&c->device) != hipSuccess) {
     delete c;
     return MFC_ERR_HIP;
@@ -332,6 +478,10 @@ int mfc_destroy(mfc_ctx* c) {
   if (c->scal) (void)hipFree(c->scal);
   if (c->partial) (void)hipFree(c->partial);
   if (c->flag) (void)hipFree(c->flag);
+  for (int d = 0; d < 3; ++d) {
+    if (c->nu_d[d]) (void)hipFree(c->nu_d[d]);
+    if (c->nu_f[d]) (void)hipFree(c->nu_f[d]);
+  }
   free_vjp_scratch(c);
   delete c->timer;
   delete c;
@@ -409,44 +559,58 @@ int mfc_max_signal(mfc_ctx* c, const void* q, double* smax_dev, void* stream) {
 }  // extern "C"
 
 namespace {
+// Device buffers one SSP-RK3 step works in: the RHS accumulator, the two
+// stage states, the reduction partials, [smax, dt] and the non-finite flag.
+struct StepScratch {
+  void* acc;
+  void* q1;
+  void* q2;
+  double* partial;
+  double* scal;
+  int* flag;
+};
+
 template <typename Real>
-hipError_t step_t(mfc_ctx* c, Real* q, double cfl, double dt_fixed, double t_remaining, double* dt_user,
-                  hipStream_t s) {
-  const int nf = c->prob.num_fluids, nd = c->prob.ndim;
+hipError_t step_t(const mfc_problem& prob, const mfc::Params& pm, const StepScratch& sc, mfc::PassTimer* tm,
+                  Real* q, double cfl, double dt_fixed, double t_remaining, double* dt_user, hipStream_t s) {
+  const int nf = prob.num_fluids, nd = prob.ndim;
   hipError_t e;
   mfc::StageArgs st{1, dt_fixed, nullptr, nullptr};
   // 2D / 3D: the first axis pass of stage 1 forms the signal maxima while it
   // loads q^n, and dt is formed on the device before the x pass reads it
-  mfc::SignalFuse sig{c->partial, cfl, t_remaining, &c->scal[0], &c->scal[1], dt_user};
+  mfc::SignalFuse sig{sc.partial, cfl, t_remaining, &sc.scal[0], &sc.scal[1], dt_user};
   const mfc::SignalFuse* sigp = nullptr;
   if (cfl > 0.0) {
     if (nd >= 2) {
       sigp = &sig;
     } else {
-      if (c->timer) c->timer->begin(mfc::KIND_SIGNAL, s);
-      e = mfc::launch_max_signal<Real>(nf, nd, c->pm, q, c->partial, &c->scal[0], cfl, t_remaining, &c->scal[1],
-                                       dt_user, c->flag, s);
-      if (c->timer) c->timer->end(mfc::KIND_SIGNAL, s);
+      if (tm) tm->begin(mfc::KIND_SIGNAL, s);
+      e = mfc::launch_max_signal<Real>(nf, nd, pm, q, sc.partial, &sc.scal[0], cfl, t_remaining, &sc.scal[1],
+                                       dt_user, sc.flag, s);
+      if (tm) tm->end(mfc::KIND_SIGNAL, s);
       if (e != hipSuccess) return e;
     }
-    st.dt_ptr = &c->scal[1];
+    st.dt_ptr = &sc.scal[1];
   } else if (dt_user) {
     e = mfc::launch_set_scalar(dt_user, dt_fixed, s);
     if (e != hipSuccess) return e;
   }
-  Real* q1 = (Real*)c->q1;
-  Real* q2 = (Real*)c->q2;
-  Real* acc = (Real*)c->acc;
+  Real* q1 = (Real*)sc.q1;
+  Real* q2 = (Real*)sc.q2;
+  Real* acc = (Real*)sc.acc;
   st.stage = 1;
-  e = mfc::launch_rhs<Real>(nf, nd, c->pm, q, acc, q, q1, st, true, c->flag, s, c->timer, sigp);
+  e = mfc::launch_rhs<Real>(nf, nd, pm, q, acc, q, q1, st, true, sc.flag, s, tm, sigp);
   if (e != hipSuccess) return e;
   st.stage = 2;
-  e = mfc::launch_rhs<Real>(nf, nd, c->pm, q1, acc, q, q2, st, true, c->flag, s, c->timer);
+  e = mfc::launch_rhs<Real>(nf, nd, pm, q1, acc, q, q2, st, true, sc.flag, s, tm);
   if (e != hipSuccess) return e;
   st.stage = 3;
-  e = mfc::launch_rhs<Real>(nf, nd, c->pm, q2, acc, q, q, st, true, c->flag, s, c->timer);
+  e = mfc::launch_rhs<Real>(nf, nd, pm, q2, acc, q, q, st, true, sc.flag, s, tm);
   return e;
 }
+
+StepScratch ctx_scratch(mfc_ctx* c) { return StepScratch{c->acc, c->q1, c->q2, c->partial, c->scal, c->flag}; }
+
 // Reverse sweep of one SSP-RK3 step given its stage states.
 hipError_t step_reverse(mfc_ctx* c, const double* qn, const double* q1, const double* q2, double dt,
                         const double* qnp1_bar, double* qn_bar, hipStream_t s) {
@@ -475,8 +639,10 @@ int mfc_step(mfc_ctx* c, void* q, double cfl, double dt_fixed, double t_remainin
     return fail(c, MFC_ERR_ARG, "non-finite step argument");
   if (dt_dev && !aligned(dt_dev, sizeof(double))) return fail(c, MFC_ERR_ARG, "misaligned dt pointer");
   hipStream_t s = (hipStream_t)stream;
-  hipError_t e = MFC_DISPATCH_REAL(c, step_t<double>(c, (double*)q, cfl, dt_fixed, t_remaining, dt_dev, s),
-                                   step_t<float>(c, (float*)q, cfl, dt_fixed, t_remaining, dt_dev, s));
+  const StepScratch sc = ctx_scratch(c);
+  hipError_t e = MFC_DISPATCH_REAL(
+      c, step_t<double>(c->prob, c->pm, sc, c->timer, (double*)q, cfl, dt_fixed, t_remaining, dt_dev, s),
+      step_t<float>(c->prob, c->pm, sc, c->timer, (float*)q, cfl, dt_fixed, t_remaining, dt_dev, s));
   return e == hipSuccess ? MFC_OK : hip_fail(c, e, "step");
 }
 
@@ -495,10 +661,65 @@ int mfc_conserved_sums(mfc_ctx* c, const void* q, double* sums_dev, void* stream
   return e == hipSuccess ? MFC_OK : hip_fail(c, e, "conserved_sums");
 }
 
+int mfc_set_grid(mfc_ctx* c, int axis, const double* faces) {
+  if (!c) return MFC_ERR_ARG;
+  if (int rd = check_device(c)) return rd;
+  if (axis < 0 || axis >= c->prob.ndim) return fail(c, MFC_ERR_ARG, "axis outside the problem's dimensions");
+  const int n = c->prob.n[axis];
+  if (faces) {
+    if (c->prob.weno_variant != MFC_WENO_JS)
+      return fail(c, MFC_ERR_UNSUPPORTED, "non-uniform grids take WENO5-JS weights");
+    for (int i = 0; i < n; ++i)
+      if (!(faces[i + 1] > faces[i]) || !std::isfinite(faces[i]) || !std::isfinite(faces[i + 1]) ||
+          !std::isfinite(faces[i + 1] - faces[i]))
+        return fail(c, MFC_ERR_ARG, "face coordinates must be finite and strictly increasing");
+  }
+  std::vector<double> keep = c->faces[axis];
+  if (faces)
+    c->faces[axis].assign(faces, faces + n + 1);
+  else
+    c->faces[axis].clear();
+  const bool any = !c->faces[0].empty() || !c->faces[1].empty() || !c->faces[2].empty();
+  if (!any) {
+    // every axis uniform again: back to the uniform kernels
+    for (int d = 0; d < 3; ++d) {
+      c->pm.nu[d] = nullptr;
+      c->pm.nuf[d] = nullptr;
+    }
+    return MFC_OK;
+  }
+  // every active axis gets a table (uniform axes: the uniform coefficients)
+  for (int d = 0; d < c->prob.ndim; ++d) {
+    std::vector<double> tab;
+    if (!build_axis_table(c->pm, d, c->faces[d], c->prob.dx[d], tab)) {
+      c->faces[axis] = keep;
+      return fail(c, MFC_ERR_ARG, "degenerate grid: a reconstruction system is singular");
+    }
+    std::vector<float> tabf(tab.begin(), tab.end());
+    const size_t nb = tab.size();
+    if (!c->nu_d[d]) {
+      if (hipMalloc((void**)&c->nu_d[d], nb * sizeof(double)) != hipSuccess ||
+          hipMalloc((void**)&c->nu_f[d], nb * sizeof(float)) != hipSuccess) {
+        (void)hipGetLastError();
+        c->faces[axis] = keep;
+        return fail(c, MFC_ERR_ALLOC, "grid table allocation failed");
+      }
+    }
+    hipError_t e = hipMemcpy(c->nu_d[d], tab.data(), nb * sizeof(double), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(c->nu_f[d], tabf.data(), nb * sizeof(float), hipMemcpyHostToDevice);
+    if (e != hipSuccess) return hip_fail(c, e, "set_grid: copy");
+    c->pm.nu[d] = c->nu_d[d];
+    c->pm.nuf[d] = c->nu_f[d];
+  }
+  return MFC_OK;
+}
+
 int mfc_rhs_vjp(mfc_ctx* c, const void* q, const void* rhs_bar, void* q_bar, int accumulate, void* stream) {
   if (!c) return MFC_ERR_ARG;
   if (int rd = check_device(c)) return rd;
   if (c->prob.precision != MFC_FP64) return fail(c, MFC_ERR_UNSUPPORTED, "adjoint entry points are FP64 only");
+  if (c->pm.nu[0] || c->pm.nu[1] || c->pm.nu[2])
+    return fail(c, MFC_ERR_UNSUPPORTED, "adjoint entry points need a uniform grid");
   int r;
   if ((r = check_array(c, q, "q")) || (r = check_array(c, rhs_bar, "rhs_bar")) || (r = check_array(c, q_bar, "q_bar")))
     return r;
@@ -514,6 +735,8 @@ int mfc_step_vjp(mfc_ctx* c, const void* q_n, double dt, const void* qnp1_bar, v
   if (!c) return MFC_ERR_ARG;
   if (int rd = check_device(c)) return rd;
   if (c->prob.precision != MFC_FP64) return fail(c, MFC_ERR_UNSUPPORTED, "adjoint entry points are FP64 only");
+  if (c->pm.nu[0] || c->pm.nu[1] || c->pm.nu[2])
+    return fail(c, MFC_ERR_UNSUPPORTED, "adjoint entry points need a uniform grid");
   int r;
   if ((r = check_array(c, q_n, "q_n")) || (r = check_array(c, qnp1_bar, "qnp1_bar")) ||
       (r = check_array(c, qn_bar, "qn_bar")))
@@ -540,6 +763,8 @@ int mfc_step_save_stages(mfc_ctx* c, void* q, double dt, void* q1, void* q2, voi
   if (!c) return MFC_ERR_ARG;
   if (int rd = check_device(c)) return rd;
   if (c->prob.precision != MFC_FP64) return fail(c, MFC_ERR_UNSUPPORTED, "adjoint entry points are FP64 only");
+  if (c->pm.nu[0] || c->pm.nu[1] || c->pm.nu[2])
+    return fail(c, MFC_ERR_UNSUPPORTED, "adjoint entry points need a uniform grid");
   int r;
   if ((r = check_array(c, q, "q")) || (r = check_array(c, q1, "q1")) || (r = check_array(c, q2, "q2"))) return r;
   if (!(dt > 0.0) || !(dt < 1e300)) return fail(c, MFC_ERR_ARG, "dt must be positive and finite");
@@ -565,6 +790,8 @@ int mfc_step_vjp_stages(mfc_ctx* c, const void* q_n, const void* q1, const void*
   if (!c) return MFC_ERR_ARG;
   if (int rd = check_device(c)) return rd;
   if (c->prob.precision != MFC_FP64) return fail(c, MFC_ERR_UNSUPPORTED, "adjoint entry points are FP64 only");
+  if (c->pm.nu[0] || c->pm.nu[1] || c->pm.nu[2])
+    return fail(c, MFC_ERR_UNSUPPORTED, "adjoint entry points need a uniform grid");
   int r;
   if ((r = check_array(c, q_n, "q_n")) || (r = check_array(c, q1, "q1")) || (r = check_array(c, q2, "q2")) ||
       (r = check_array(c, qnp1_bar, "qnp1_bar")) || (r = check_array(c, qn_bar, "qn_bar")))

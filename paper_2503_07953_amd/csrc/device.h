@@ -21,13 +21,39 @@ struct Params {
   int bc_hi[3];        // BC kind per axis, high side
   int weno_variant;    // 0: WENO5-JS, 1: WENO5-Z, 2: TENO5, 3: WENO5-M
   int riemann;         // 0: HLLC, 1: HLL (Sec. 3.2.2)
-  int low_mach;        // 0: none, 1: Thornber et al. velocity correction
+  int low_mach;        // 0: none, 1: Thornber et al. velocity correction, 2: Chen et al. APC
+  int model;           // 0: Allaire (K = 0), 1: Kapila (K div u on the alpha rows)
   double inv_dx[3];    // 1/dx per axis
   double G[2];         // 1/(gamma_i - 1)
   double P[2];         // gamma_i pi_inf,i/(gamma_i - 1)
+  double gam[2];       // gamma_i
+  double pinf[2];      // pi_inf,i
   double eps;          // WENO regularization
   long long ncell;     // nx*ny*nz: stride between rows
+  // Non-uniform grid (set by mfc_set_grid): per axis, a table of kNuCoefs rows
+  // of n + 6 entries (positions -3 .. n + 2), in double and in float; null on
+  // a uniform grid.
+  const double* nu[3];
+  const float* nuf[3];
 };
+
+// Rows of the non-uniform reconstruction table of one axis (entry pos + 3 for
+// the centre cell at position pos).  In the centre cell's unit coordinate
+// xi = (x - x_c)/h_c, candidate r (cells c - 2 + r .. c + r) is the quadratic
+// m0 + m1 xi + m2 xi^2 whose cell averages are the data; with D_k = f_{k+1} -
+// f_k over the five cells f_0 .. f_4 (centre f_2), m0 - f_2, m1 and m2 are
+// combinations a D_r + b D_{r+1} of the stencil's two differences:
+//   NU_MU0 + 2 r (+1): a, b of m0 - f_2;  NU_M1 + 2 r (+1): of m1;
+//   NU_M2 + 2 r (+1): of m2;
+//   NU_DR + r: ideal weight of candidate r at the right face (xi = 1/2);
+//   NU_DL + r: at the left face (xi = -1/2);
+//   NU_INVW: 1/h of the cell at that position.
+enum { NU_MU0 = 0, NU_M1 = 6, NU_M2 = 12, NU_DR = 18, NU_DL = 21, NU_INVW = 24, kNuCoefs = 25 };
+
+// 1/h of cell i along axis d (uniform or tabulated).
+__host__ __device__ __forceinline__ double inv_width(const Params& pm, int d, int i) {
+  return pm.nu[d] ? pm.nu[d][(long long)NU_INVW * (pm.n[d] + 6) + i + 3] : pm.inv_dx[d];
+}
 
 // Row layout for NF fluids in D dimensions.
 template <int NF, int D>
@@ -123,6 +149,21 @@ __host__ __device__ __forceinline__ void cons_to_prim(const Params& pm, const do
 // gamma_m = 1 + 1/Gamma, pi_m = Pi/(Gamma + 1): c^2 = ((Gamma+1) p + Pi)/(Gamma rho).
 __host__ __device__ __forceinline__ double sound_speed_sq(double rho, double p, double Gam, double Pi) {
   return ((Gam + 1.0) * p + Pi) * fast_rcp(Gam * rho);
+}
+
+// Kapila's K of one cell (Sec. 2.1.1): the alpha_1 row carries
+// (alpha_1 + K) div u and the alpha_2 row (alpha_2 - K) div u, with
+//   K = (rho_2 c_2^2 - rho_1 c_1^2) / (rho_1 c_1^2/alpha_1 + rho_2 c_2^2/alpha_2)
+// and phasic sound speeds c_i^2 = gamma_i (p + pi_inf,i)/rho_i, so that
+// rho_i c_i^2 = gamma_i (p + pi_inf,i) needs no phasic density.  The numerator
+// is the difference of the two phases' stiffnesses: K vanishes for identical
+// fluids.  Double arithmetic from the cell's pressure and volume fractions,
+// over the common denominator: K = (z_2 - z_1) alpha_1 alpha_2 / (z_1 alpha_2 +
+// z_2 alpha_1) with z_i = gamma_i (p + pi_inf,i).
+__host__ __device__ __forceinline__ double kapila_K(const Params& pm, double p, double a1, double a2) {
+  const double z1 = pm.gam[0] * (p + pm.pinf[0]);
+  const double z2 = pm.gam[1] * (p + pm.pinf[1]);
+  return (z2 - z1) * (a1 * a2) * fast_rcp(z1 * a2 + z2 * a1);
 }
 
 // ---------------------------------------------------------------------------
@@ -420,6 +461,66 @@ __device__ __forceinline__ void weno5_m(float a, float b, float c, float d, floa
   fr = c + (er0 * r0 + er1 * r1 + er2 * r2) * __builtin_amdgcn_rcpf(6.0f * (er0 + er1 + er2));
 }
 
+// ---------------------------------------------------------------------------
+// WENO5-JS on a non-uniform grid (Sec. 4.2.2): the candidates and smoothness
+// indicators of the centre's tabulated quadratics and the grid's ideal weights.
+// In the unit coordinate of the centre cell the candidate values at the right
+// and left faces are f_2 + m0' +- m1/2 + m2/4 (m0' = m0 - f_2) and the
+// indicator sum_{l=1,2} h^(2l-1) int (d^l p/dx^l)^2 dx is m1^2 + (13/3) m2^2.
+// `cf` points at the centre's entry of row 0 and `st` is the row stride.
+// fr: value at the right face (left state of the face c + 1/2); fl: value at
+// the left face (right state of the face c - 1/2).
+// ---------------------------------------------------------------------------
+template <typename T, typename C>
+__device__ __forceinline__ void nu_candidates(const T* D, const C* cf, long long st, T* qr, T* ql, T* beta) {
+#pragma unroll
+  for (int r = 0; r < 3; ++r) {
+    const T da = D[r], db = D[r + 1];
+    const T mu0 = T(cf[(NU_MU0 + 2 * r) * st]) * da + T(cf[(NU_MU0 + 2 * r + 1) * st]) * db;
+    const T m1 = T(cf[(NU_M1 + 2 * r) * st]) * da + T(cf[(NU_M1 + 2 * r + 1) * st]) * db;
+    const T m2 = T(cf[(NU_M2 + 2 * r) * st]) * da + T(cf[(NU_M2 + 2 * r + 1) * st]) * db;
+    const T even = mu0 + T(0.25) * m2;
+    qr[r] = even + T(0.5) * m1;
+    ql[r] = even - T(0.5) * m1;
+    beta[r] = m1 * m1 + T(13.0 / 3.0) * (m2 * m2);
+  }
+}
+
+// Double: the weights d_r/(eps + beta_r)^2 over the common denominator
+// t0 t1 t2, both normalizations from one refined reciprocal (as weno5_js).
+__device__ __forceinline__ void weno5_nu(double a, double b, double c, double d, double e, double eps,
+                                         const double* cf, long long st, double& fr, double& fl) {
+  const double D[4] = {b - a, c - b, d - c, e - d};
+  double qr[3], ql[3], beta[3];
+  nu_candidates<double, double>(D, cf, st, qr, ql, beta);
+  const double t0 = sq(eps + beta[0]), t1 = sq(eps + beta[1]), t2 = sq(eps + beta[2]);
+  const double p0 = t1 * t2, p1 = t0 * t2, p2 = t0 * t1;
+  const double wr0 = cf[(NU_DR + 0) * st] * p0, wr1 = cf[(NU_DR + 1) * st] * p1, wr2 = cf[(NU_DR + 2) * st] * p2;
+  const double wl0 = cf[(NU_DL + 0) * st] * p0, wl1 = cf[(NU_DL + 1) * st] * p1, wl2 = cf[(NU_DL + 2) * st] * p2;
+  const double sr = wr0 + wr1 + wr2, sl = wl0 + wl1 + wl2;
+  const double inv = fast_rcp(sr * sl);
+  fr = c + (wr0 * qr[0] + wr1 * qr[1] + wr2 * qr[2]) * (sl * inv);
+  fl = c + (wl0 * ql[0] + wl1 * ql[1] + wl2 * ql[2]) * (sr * inv);
+}
+
+// Float: the weights from the ratios s_min/s_r, s_r = eps + beta_r (as the
+// float weno5_js), each side normalized on its own.
+__device__ __forceinline__ void weno5_nu(float a, float b, float c, float d, float e, float eps, const float* cf,
+                                         long long st, float& fr, float& fl) {
+  const float D[4] = {b - a, c - b, d - c, e - d};
+  float qr[3], ql[3], beta[3];
+  nu_candidates<float, float>(D, cf, st, qr, ql, beta);
+  const float s0 = eps + beta[0], s1 = eps + beta[1], s2 = eps + beta[2];
+  const float sm = fminf(s0, fminf(s1, s2));
+  const float a0 = sq(sm * __builtin_amdgcn_rcpf(s0));
+  const float a1 = sq(sm * __builtin_amdgcn_rcpf(s1));
+  const float a2 = sq(sm * __builtin_amdgcn_rcpf(s2));
+  const float wr0 = cf[(NU_DR + 0) * st] * a0, wr1 = cf[(NU_DR + 1) * st] * a1, wr2 = cf[(NU_DR + 2) * st] * a2;
+  const float wl0 = cf[(NU_DL + 0) * st] * a0, wl1 = cf[(NU_DL + 1) * st] * a1, wl2 = cf[(NU_DL + 2) * st] * a2;
+  fr = c + (wr0 * qr[0] + wr1 * qr[1] + wr2 * qr[2]) * __builtin_amdgcn_rcpf(wr0 + wr1 + wr2);
+  fl = c + (wl0 * ql[0] + wl1 * ql[1] + wl2 * ql[2]) * __builtin_amdgcn_rcpf(wl0 + wl1 + wl2);
+}
+
 // Maximum over the 64 lanes of a wave (NaN-ignoring, as fmax).
 __device__ __forceinline__ double wave_max(double v) {
 #pragma unroll
@@ -431,7 +532,8 @@ __device__ __forceinline__ double wave_max(double v) {
 // conservative U and primitive W of the cell (c: frozen-mixture sound speed).
 // bad: c^2 <= 0 or a non-finite result.
 template <int NF, int D>
-__device__ __forceinline__ double cell_signal(const Params& pm, const double* U, const double* W, bool& bad) {
+__device__ __forceinline__ double cell_signal(const Params& pm, const double* U, const double* W, bool& bad,
+                                              const double* inv_h) {
   using R = Rows<NF, D>;
   double rho = U[0];
   if constexpr (NF == 2) rho = U[0] + U[1];
@@ -444,7 +546,7 @@ __device__ __forceinline__ double cell_signal(const Params& pm, const double* U,
   const double cs = sqrt(c2);
   double s = 0.0;
 #pragma unroll
-  for (int d = 0; d < D; ++d) s += (fabs(W[R::MOM + d]) + cs) * pm.inv_dx[d];
+  for (int d = 0; d < D; ++d) s += (fabs(W[R::MOM + d]) + cs) * inv_h[d];
   bad = !(c2 > 0.0) || !isfinite(s);
   return s;
 }
@@ -474,7 +576,7 @@ __device__ __forceinline__ void weno5(T a, T b, T c, T d, T e, T eps, T& fl, T& 
 //   volume fractions are carried by the contact: flux alpha_K u_f.
 // Returns true when a side has c^2 <= 0 or a flux is not finite.
 // ---------------------------------------------------------------------------
-template <int NF, int D, int DIR, typename T>
+template <int NF, int D, int DIR, typename T, bool APC = false>
 __host__ __device__ __forceinline__ bool hllc(const Params& pm, const T* WL, const T* WR, T* F, T& uf) {
   using R = Rows<NF, D>;
   // side quantities
@@ -502,8 +604,8 @@ __host__ __device__ __forceinline__ bool hllc(const Params& pm, const T* WL, con
   const double SR = (sra >= srb) ? sra : srb;
   const double drhoL = double(rhoL), drhoR = double(rhoR);
   // the denominator is strictly negative for physical states (S_L < u_L, S_R > u_R)
-  const double Sstar = (double(pR) - double(pL) + drhoL * dunL * (SL - dunL) - drhoR * dunR * (SR - dunR)) *
-                       -fast_rcp(drhoR * (SR - dunR) - drhoL * (SL - dunL));
+  const double rden = fast_rcp(drhoR * (SR - dunR) - drhoL * (SL - dunL));
+  const double Sstar = (double(pR) - double(pL) + drhoL * dunL * (SL - dunL) - drhoR * dunR * (SR - dunR)) * -rden;
 
   // side the face takes and whether it lies in the star region
   const bool useL = (SL >= 0.0) || (Sstar >= 0.0);
@@ -533,6 +635,21 @@ __host__ __device__ __forceinline__ bool hllc(const Params& pm, const T* WL, con
   const T s = star ? T(SK) : T(0);
   const T chiT = T(chi);
   const T SstarT = T(Sstar);
+  // anti-dissipation pressure correction of Chen et al. (Sec. 4.2.4) on both
+  // star fluxes: (z - 1) p_d on the normal momentum and (z - 1) p_d S* on the
+  // energy, with p_d = rho_L rho_R (S_L - u_L)(S_R - u_R)(u_R - u_L) /
+  // (rho_R (S_R - u_R) - rho_L (S_L - u_L)) (the velocity-jump part of the star
+  // pressure) and z = min(max(|u_L|/c_L, |u_R|/c_R), 1); double arithmetic
+  T apc_m = T(0), apc_e = T(0);
+  if constexpr (APC) {
+    const double mL = fabs(dunL) * fast_rcp(cL), mR = fabs(dunR) * fast_rcp(cR);
+    double z = (mL >= mR) ? mL : mR;
+    if (z > 1.0) z = 1.0;
+    const double pd = drhoL * drhoR * (SL - dunL) * (SR - dunR) * (dunR - dunL) * rden;
+    const double am = star ? (z - 1.0) * pd : 0.0;
+    apc_m = T(am);
+    apc_e = T(am * Sstar);
+  }
 #pragma unroll
   for (int i = 0; i < NF; ++i) {
     const T Ui = W[i];
@@ -547,6 +664,10 @@ __host__ __device__ __forceinline__ bool hllc(const Params& pm, const T* WL, con
   {
     const T Es = chiT * (E + (SstarT - un) * (rho * SstarT + T(p_over)));
     F[R::E] = (E + p) * un + s * (Es - E);
+  }
+  if constexpr (APC) {
+    F[R::MOM + DIR] = F[R::MOM + DIR] + apc_m;
+    F[R::E] = F[R::E] + apc_e;
   }
   uf = star ? SstarT : un;
   if constexpr (NF == 2) {
@@ -677,13 +798,17 @@ __host__ __device__ __forceinline__ void thornber(const Params& pm, T* WL, T* WR
   WR[R::MOM + DIR] = T(0.5 * (uL + uR) + z * (0.5 * (uR - uL)));
 }
 
-// The face solver of a kernel instantiation: RS = 0 HLLC, 1 HLL.
+// Compile-time face options of a kernel instantiation (bits of RS).
+enum { RS_HLL = 1, RS_THORNBER = 2, RS_APC = 4, RS_KAPILA = 8 };
+
+// The face solver of a kernel instantiation: HLL when RS has RS_HLL, else
+// HLLC, with the APC term when RS has RS_APC.
 template <int RS, int NF, int D, int DIR, typename T>
 __host__ __device__ __forceinline__ bool riemann(const Params& pm, const T* WL, const T* WR, T* F, T& uf) {
-  if constexpr (RS == 1)
+  if constexpr ((RS & RS_HLL) != 0)
     return hll<NF, D, DIR, T>(pm, WL, WR, F, uf);
   else
-    return hllc<NF, D, DIR, T>(pm, WL, WR, F, uf);
+    return hllc<NF, D, DIR, T, (RS & RS_APC) != 0>(pm, WL, WR, F, uf);
 }
 
 }  // namespace mfc

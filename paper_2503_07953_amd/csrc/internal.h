@@ -33,6 +33,16 @@ struct SignalFuse {
   double* dt_user;
 };
 
+// Internal reconstruction variant of the axis passes on a non-uniform grid
+// (WENO5-JS with tabulated coefficients); 0..3 are the uniform variants.
+constexpr int kWvNonUniform = 4;
+
+// Compile-time option bits of a problem (RS_HLL, RS_THORNBER, RS_APC, RS_KAPILA).
+inline int option_bits(const Params& pm) {
+  return (pm.riemann == 1 ? RS_HLL : 0) | (pm.low_mach == 1 ? RS_THORNBER : 0) | (pm.low_mach == 2 ? RS_APC : 0) |
+         (pm.model == 1 ? RS_KAPILA : 0);
+}
+
 // Kinds of timed launches (see mfc_set_timing).
 enum { KIND_SIGNAL = 0, KIND_PASS_X = 1, KIND_PASS_Y = 2, KIND_PASS_Z = 3, KIND_VJP = 4, KIND_COUNT = 5 };
 

@@ -33,8 +33,14 @@ __global__ __launch_bounds__(kReduceThreads) void max_signal_partial(Params pm, 
 #pragma unroll
     for (int v = 0; v < NEQ; ++v) U[v] = double(q[v * nc + c]);
     cons_to_prim<NF, D>(pm, U, W);
+    // 1/h per axis of this cell (tabulated on a non-uniform grid)
+    const long long nx = pm.n[0], ny = pm.n[1];
+    const int idx[3] = {(int)(c % nx), (int)((c / nx) % ny), (int)(c / (nx * ny))};
+    double ih[D];
+#pragma unroll
+    for (int d = 0; d < D; ++d) ih[d] = inv_width(pm, d, idx[d]);
     bool b;
-    const double s = cell_signal<NF, D>(pm, U, W, b);
+    const double s = cell_signal<NF, D>(pm, U, W, b, ih);
     bad |= b;
     smax = (s > smax) ? s : smax;  // NaN never wins; it is flagged instead
   }
@@ -110,8 +116,11 @@ hipError_t launch_max_signal(int nf, int ndim, const Params& pm, const Real* q, 
   return hipGetLastError();
 }
 
-template <typename Real>
-__global__ __launch_bounds__(kReduceThreads) void sums_partial(int neq, long long nc, const Real* __restrict__ q,
+// Block sums of each row; on a non-uniform grid (NU) every cell is weighted by
+// its own volume h_x h_y h_z (the finalize pass then scales by 1).
+template <typename Real, bool NU>
+__global__ __launch_bounds__(kReduceThreads) void sums_partial(Params pm, int neq, long long nc,
+                                                               const Real* __restrict__ q,
                                                                double* __restrict__ partial) {
   const long long chunk = (nc + gridDim.x - 1) / gridDim.x;
   const long long beg = (long long)blockIdx.x * chunk;
@@ -119,7 +128,16 @@ __global__ __launch_bounds__(kReduceThreads) void sums_partial(int neq, long lon
   __shared__ double red[kReduceThreads / 64];
   for (int v = 0; v < neq; ++v) {
     double acc = 0.0;
-    for (long long c = beg + threadIdx.x; c < end; c += blockDim.x) acc += double(q[v * nc + c]);
+    for (long long c = beg + threadIdx.x; c < end; c += blockDim.x) {
+      if constexpr (NU) {
+        const long long nx = pm.n[0], ny = pm.n[1];
+        const double w = (1.0 / inv_width(pm, 0, (int)(c % nx))) * (1.0 / inv_width(pm, 1, (int)((c / nx) % ny))) *
+                         (1.0 / inv_width(pm, 2, (int)(c / (nx * ny))));
+        acc += double(q[v * nc + c]) * w;
+      } else {
+        acc += double(q[v * nc + c]);
+      }
+    }
     acc = wave_sum(acc);
     if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
     __syncthreads();
@@ -144,11 +162,16 @@ __global__ void sums_finalize(int neq, int nparts, double vol, const double* __r
 template <typename Real>
 hipError_t launch_sums(int neq, const Params& pm, const Real* q, double vol, double* partial, double* sums_out,
                        hipStream_t s) {
-  hipLaunchKernelGGL((sums_partial<Real>), dim3(kReduceBlocks), dim3(kReduceThreads), 0, s, neq, pm.ncell, q,
-                     partial);
+  const bool nu = pm.nu[0] || pm.nu[1] || pm.nu[2];
+  if (nu)
+    hipLaunchKernelGGL((sums_partial<Real, true>), dim3(kReduceBlocks), dim3(kReduceThreads), 0, s, pm, neq,
+                       pm.ncell, q, partial);
+  else
+    hipLaunchKernelGGL((sums_partial<Real, false>), dim3(kReduceBlocks), dim3(kReduceThreads), 0, s, pm, neq,
+                       pm.ncell, q, partial);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(sums_finalize, dim3(1), dim3(64), 0, s, neq, kReduceBlocks, vol, partial, sums_out);
+  hipLaunchKernelGGL(sums_finalize, dim3(1), dim3(64), 0, s, neq, kReduceBlocks, nu ? 1.0 : vol, partial, sums_out);
   return hipGetLastError();
 }
 

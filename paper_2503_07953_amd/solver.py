@@ -24,15 +24,12 @@ class Solver:
     """Owns one mfc_ctx.  `precision` is "fp64" or "fp32" (the mixed FP32 form)."""
 
     def __init__(self, ndim, n, num_fluids, dx, gamma, pi_inf, bc_lo, bc_hi, weno_eps=1e-6,
-                 precision="fp64", device="cuda", weno_variant=0, riemann=0, low_mach=0, model=0):
+                 precision="fp64", device="cuda", weno_variant=0, riemann=0, low_mach=0, model=0, faces=None):
         self.lib = L.load()
-        if model != 0 or low_mach == 2:
-            raise L.MfcError(L.MFC_ERR_UNSUPPORTED, "the Kapila model and the APC correction are not in this "
-                                                    "library version")
         self.precision = precision
         prec = L.MFC_FP64 if precision == "fp64" else L.MFC_FP32_MIXED
         self.prob = L.make_problem(ndim, n, num_fluids, dx, gamma, pi_inf, bc_lo, bc_hi, weno_eps, prec, weno_variant,
-                                   riemann, low_mach)
+                                   riemann, low_mach, model)
         self.dtype = torch.float64 if precision == "fp64" else torch.float32
         self.device = torch.device(device)
         rc = self.lib.mfc_validate(ctypes.byref(self.prob))
@@ -51,6 +48,10 @@ class Solver:
             raise L.MfcError(rc, "mfc_create")
         self.ctx = h
         self._dev_index = self.device.index if self.device.index is not None else torch.cuda.current_device()
+        if faces is not None:
+            for d, f in enumerate(faces):
+                if f is not None:
+                    self.set_grid(d, f)
         self._scal = torch.zeros(4, dtype=torch.float64, device=self.device)
 
     @classmethod
@@ -112,6 +113,19 @@ class Solver:
         out = torch.empty(1, dtype=torch.float64, device=self.device)
         self._check(self.lib.mfc_max_signal(self.ctx, _ptr(q), _ptr(out), _stream()), "mfc_max_signal")
         return out
+
+    def set_grid(self, axis, faces):
+        """Non-uniform grid along `axis`: its n + 1 face coordinates (host
+        array), or None for uniform spacing again."""
+        if faces is None:
+            ptr = None
+        else:
+            self._faces_host = getattr(self, "_faces_host", {})
+            a = (ctypes.c_double * len(faces))(*[float(v) for v in faces])
+            self._faces_host[axis] = a
+            ptr = ctypes.cast(a, ctypes.c_void_p)
+        with torch.cuda.device(self.device):
+            self._check(self.lib.mfc_set_grid(self.ctx, int(axis), ptr), "mfc_set_grid")
 
     def step(self, q, cfl=0.0, dt_fixed=0.0, t_remaining=0.0, dt_out=None):
         """Advance q in place by one SSP-RK3 step.  dt_out: optional device double tensor."""

@@ -84,14 +84,16 @@ def noise_floor(fn, q, trials=3, seed=5):
     return base, spread
 
 
-def rate_errors(a, b, q, smax, nf, ndim):
+def rate_errors(a, b, q, smax, nf, ndim, mom_rate=None):
     """RHS error per conservative field on the scale of the field's fastest rate.
 
     A right-hand side is a difference of face fluxes; its rounding error is
     relative to the fluxes, |F_v| <= |q_v| (|u| + c), not to the difference,
     which is pure rounding noise wherever the exact RHS vanishes (fluid at rest
     in uniform pressure).  Scale: max|q_v| * s_max with s_max = max over cells
-    of sum_d (|u_d| + c)/dx_d.  Momentum is one vector field.
+    of sum_d (|u_d| + c)/dx_d.  Momentum is one vector field; its flux also
+    carries the pressure, so for a state at rest (zero momentum) the caller
+    passes the momentum scale, e.g. max p / dx, as ``mom_rate``.
     """
     a = np.asarray(a, dtype=np.float64)
     b = np.asarray(b, dtype=np.float64)
@@ -101,7 +103,8 @@ def rate_errors(a, b, q, smax, nf, ndim):
         out.append(np.abs(a[i] - b[i]).max() / (np.abs(q[i]).max() * smax))
     m = slice(nf, nf + ndim)
     num = np.sqrt(((a[m] - b[m]) ** 2).sum(axis=0)).max()
-    out.append(num / (np.sqrt((q[m] ** 2).sum(axis=0)).max() * smax))
+    den = np.sqrt((q[m] ** 2).sum(axis=0)).max() * smax if mom_rate is None else mom_rate
+    out.append(num / den)
     for r in range(nf + ndim, b.shape[0]):
         out.append(np.abs(a[r] - b[r]).max() / (np.abs(q[r]).max() * smax))
     return np.array(out)

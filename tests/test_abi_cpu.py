@@ -79,7 +79,14 @@ def test_num_eqs(L):
     (dict(riemann=2), -3),
     (dict(riemann=-1), -3),
     (dict(low_mach=1), 0),
-    (dict(low_mach=2), -3),
+    (dict(low_mach=2), 0),
+    (dict(low_mach=2, riemann=1), -3),
+    (dict(low_mach=3), -3),
+    (dict(model=1), 0),
+    (dict(model=1, low_mach=2), 0),
+    (dict(model=1, num_fluids=1), -3),
+    (dict(model=2), -3),
+    (dict(model=-1), -3),
 ])
 def test_validation_codes(L, kw, code):
     lib = L.load()
@@ -118,3 +125,23 @@ def test_missing_library_fails_loudly(tmp_path, monkeypatch):
     from paper_2503_07953_amd.solver import Solver
     with pytest.raises(_lib.LibraryMissing):
         Solver(1, (8,), 1, (0.1,), (1.4, 1.4), (0.0, 0.0), (1,), (1,))
+
+
+def test_solver_takes_every_problem_field():
+    """Solver.from_case passes the whole problem description (every key of
+    Case.problem_kwargs) to the constructor, which must accept each one."""
+    import inspect
+
+    import workloads as W
+    from paper_2503_07953_amd.solver import Solver
+    params = inspect.signature(Solver.__init__).parameters
+    c = W.random_case(2, (8, 8), nf=2, seed=0)
+    c.faces = (W.stretched_faces(8), None, None)
+    keys = c.problem_kwargs().keys()
+    assert not [k for k in keys if k not in params]
+
+
+def test_set_grid_needs_a_context(L):
+    lib = L.load()
+    buf = (ctypes.c_double * 9)(*range(9))
+    assert lib.mfc_set_grid(None, 0, ctypes.cast(buf, ctypes.c_void_p)) == L.MFC_ERR_ARG

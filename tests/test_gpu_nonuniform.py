@@ -1,0 +1,174 @@
+"""Non-uniform grids (Sec. 4.2.2) in the HIP library, through the C ABI,
+against the CPU FP64 oracle: RHS and 5 CFL steps at the FP64 parity bar,
+equally spaced faces against the uniform path, signal speed and conservation
+sums with per-cell widths, the FP32 form inside its float envelope, and the
+argument checks of mfc_set_grid.
+"""
+import ctypes
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+from helpers import conservative_errors, grouped_errors
+from test_gpu_parity import CASES, _variant_steps_match
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-12
+EPS32 = 2.0 ** -24
+
+
+def _say(*a):
+    print("[gpu-nonuniform]", *a, flush=True)
+
+
+def _solver(case, precision="fp64"):
+    from paper_2503_07953_amd.solver import Solver
+    return Solver.from_case(case, precision=precision)
+
+
+def _stretch(c, amps, seed=0):
+    """Put case c on a stretched grid: per active axis the smooth map of
+    workloads.stretched_faces with amplitude amps[d] (None: keep uniform),
+    over the axis's own length n dx."""
+    faces = []
+    for d in range(3):
+        a = amps[d] if d < len(amps) else None
+        if d >= c.ndim or a is None:
+            faces.append(None)
+        else:
+            faces.append(W.stretched_faces(c.n[d], c.n[d] * c.dx[d], a))
+    c.faces = tuple(faces)
+    return c
+
+
+# (CASES index, stretch amplitude per axis)
+NU_CASES = [
+    (0, (0.5,)),                  # 1D one fluid, extrapolation
+    (1, (-0.4,)),                 # 1D two fluids, slip walls
+    (2, (0.3,)),                  # 1D two fluids, periodic
+    (3, (0.5, -0.3)),             # 2D two fluids, extrapolation x slip wall
+    (4, (None, 0.4)),             # 2D one fluid, y stretched only
+    (5, (0.4, 0.4)),              # 2D two fluids, periodic
+    (6, (0.3, -0.5, 0.4)),        # 3D two fluids, every boundary kind
+    (7, (0.5, None, -0.3)),       # 3D one fluid
+    (8, (0.2, 0.2, 0.2)),         # 3D, three cells per axis
+]
+
+
+@pytest.mark.parametrize("case,amps", NU_CASES)
+def test_nonuniform_rhs_and_steps_match_oracle(case, amps):
+    nd, n, nf, bc = CASES[case]
+    _say("nonuniform", nd, n, nf, bc, amps)
+    c = W.random_case(nd, n, nf=nf, seed=1000 + case, bc=bc, speed=400.0 if nf == 1 else 150.0)
+    _stretch(c, amps)
+    _variant_steps_match(c, nf, nd)
+
+
+@pytest.mark.parametrize("name", ["shock_cylinder_64", "bubble_cloud_48"])
+def test_nonuniform_two_fluid_flows_match_oracle(name):
+    """The benchmark flows on centre-clustered grids (width ratio 3 and 2)."""
+    if name.startswith("shock"):
+        c = _stretch(W.shock_cylinder(64), (-0.5, -0.5))
+        zero = (1,)
+    else:
+        c = _stretch(W.bubble_cloud(48, nbub=4), (-0.33, -0.33, -0.33))
+        zero = (1, 2)
+    _say("nonuniform flow", name)
+    _variant_steps_match(c, 2, c.ndim, flux_scale=True, zero_mom=zero)
+
+
+def test_equally_spaced_faces_match_the_uniform_path():
+    """Face coordinates at equal spacing give the uniform kernels' RHS and
+    steps to rounding (different kernels and arithmetic: tabulated
+    coefficients instead of constants)."""
+    c = W.random_case(3, (40, 36, 30), nf=2, seed=1011, bc=(W.EXTRAP, W.SLIPWALL, W.PERIODIC), speed=150.0)
+    Su = _solver(c)
+    qu = Su.prim_to_cons(Su.to_device(c.w))
+    ru = Su.rhs(qu).cpu().numpy()
+    c.faces = tuple(np.arange(c.n[d] + 1) * c.dx[d] for d in range(3))
+    Sn = _solver(c)
+    qn = Sn.prim_to_cons(Sn.to_device(c.w))
+    rn = Sn.rhs(qn).cpu().numpy()
+    Su.run(qu, 3, cfl=0.5)
+    Sn.run(qn, 3, cfl=0.5)
+    Su.check()
+    Sn.check()
+    e1 = conservative_errors(rn, ru, 2, 3)
+    e2 = conservative_errors(qn.cpu().numpy(), qu.cpu().numpy(), 2, 3)
+    _say("equal spacing vs uniform", e1, e2)
+    assert e1.max() <= 1e-12 and e2.max() <= 1e-12, (e1, e2)
+    # and back to uniform spacing: the uniform kernels again, bitwise
+    for d in range(3):
+        Sn.set_grid(d, None)
+    q2 = Sn.prim_to_cons(Sn.to_device(c.w))
+    assert np.array_equal(Sn.rhs(q2).cpu().numpy(), ru)
+
+
+def test_nonuniform_signal_and_sums_match_oracle():
+    c = _stretch(W.random_case(3, (40, 36, 30), nf=2, seed=1012, bc=(W.EXTRAP, W.SLIPWALL, W.PERIODIC),
+                               speed=300.0), (0.5, -0.4, 0.3))
+    O = oracle.Oracle(c)
+    q = O.prim_to_cons(c.w)
+    S = _solver(c)
+    qd = S.to_device(q)
+    s = S.max_signal(qd).item()
+    assert abs(s / O.max_signal(q) - 1) <= 1e-13
+    sums = S.conserved_sums(qd).cpu().numpy()
+    ref = O.conserved_sums(q)
+    assert np.all(np.abs(sums - ref) <= 1e-13 * np.abs(ref) + 1e-300), (sums, ref)
+
+
+@pytest.mark.parametrize("kind", ["random", "bubbles"])
+def test_fp32_nonuniform_within_float_envelope(kind):
+    """The FP32 form on a stretched grid (float coefficients) against the FP64
+    oracle, inside the float envelope of the uniform FP32 tests with the
+    smallest width in the momentum bound."""
+    if kind == "bubbles":
+        c = _stretch(W.bubble_cloud(64, nbub=6, slab=8), (-0.3, -0.3, -0.3))
+        nsteps = 20
+    else:
+        c = _stretch(W.random_case(3, (40, 36, 30), nf=2, seed=5, bc=(W.EXTRAP, W.SLIPWALL, W.PERIODIC),
+                                   speed=100.0), (0.4, -0.4, 0.3))
+        nsteps = 10
+    O = oracle.Oracle(c)
+    q = O.prim_to_cons(c.w)
+    dts = O.run(q, nsteps, cfl=0.5)
+    S = _solver(c, precision="fp32")
+    q32 = S.prim_to_cons(S.to_device(c.w))
+    S.run(q32, nsteps, cfl=0.5)
+    S.check()
+    err = grouped_errors(q32.double().cpu().numpy(), q, 2, 3)
+    stages = 3 * nsteps
+    hmin = min(np.diff(f).min() for f in c.faces if f is not None)
+    gam_w = 1.0 / (c.gamma[0] - 1.0)
+    mom = np.sqrt((q[2:5] ** 2).sum(axis=0)).max()
+    bound = np.full(6, 4 * stages * EPS32)
+    bound[2] = max(4 * stages * 3 * EPS32 * np.abs(q[5]).max() * (dts.max() / hmin) / (gam_w * mom), bound[0])
+    _say(kind, "errors", err, "bounds", bound)
+    assert np.all(err <= bound), (err, bound)
+
+
+def test_set_grid_argument_checks():
+    from paper_2503_07953_amd import _lib as L
+    c = W.random_case(2, (20, 16), nf=2, seed=1013, bc=(W.EXTRAP, W.EXTRAP), speed=100.0)
+    S = _solver(c)
+    lib = S.lib
+    good = (ctypes.c_double * 21)(*np.linspace(0.0, 1.0, 21))
+    bad = (ctypes.c_double * 21)(*np.linspace(0.0, 1.0, 21))
+    bad[7] = bad[6]
+    assert lib.mfc_set_grid(S.ctx, 0, ctypes.cast(bad, ctypes.c_void_p)) == L.MFC_ERR_ARG
+    assert lib.mfc_set_grid(S.ctx, 2, ctypes.cast(good, ctypes.c_void_p)) == L.MFC_ERR_ARG
+    assert lib.mfc_set_grid(S.ctx, -1, ctypes.cast(good, ctypes.c_void_p)) == L.MFC_ERR_ARG
+    assert lib.mfc_set_grid(None, 0, ctypes.cast(good, ctypes.c_void_p)) == L.MFC_ERR_ARG
+    assert lib.mfc_set_grid(S.ctx, 0, ctypes.cast(good, ctypes.c_void_p)) == L.MFC_OK
+    # the RHS and step adjoints need a uniform grid
+    q = S.prim_to_cons(S.to_device(c.w))
+    with pytest.raises(L.MfcError) as e:
+        S.rhs_vjp(q, q.clone())
+    assert e.value.code == L.MFC_ERR_UNSUPPORTED
+    # other reconstruction weights take no grid
+    c.weno_variant = 1
+    Sz = _solver(c)
+    assert Sz.lib.mfc_set_grid(Sz.ctx, 0, ctypes.cast(good, ctypes.c_void_p)) == L.MFC_ERR_UNSUPPORTED

@@ -452,7 +452,10 @@ def test_bubble_cloud_256_full_size_step_and_sampled_rhs():
     S.step(qd, cfl=0.5)
     S.check()
     O.step(q, cfl=0.5)
-    err = conservative_errors(qd.cpu().numpy(), q, 2, 3)
+    # after one step the pulse is still a planar wave along x and the bubbles
+    # sit at rest in uniform pressure (the pulse starts 4 + r cells before the
+    # nearest bubble): the y and z momentum are zero in exact arithmetic
+    err = conservative_errors(qd.cpu().numpy(), q, 2, 3, zero_mom=(1, 2))
     _say("C2 step errors", err)
     assert err.max() <= TOL, err
 
