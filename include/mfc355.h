@@ -187,6 +187,30 @@ int mfc_max_signal(mfc_ctx* ctx, const void* q, double* smax_dev, void* hip_stre
 int mfc_step(mfc_ctx* ctx, void* q, double cfl, double dt_fixed, double t_remaining,
              double* dt_dev, void* hip_stream);
 
+/* For callers that cannot allocate device memory: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc.  The step of
+ * mfc_step (same kernels, same results bit for bit) without a context: the
+ * RHS accumulator, both stage states, the reduction partials and [smax, dt]
+ * live in one static device array of MFC_STATIC_SCRATCH_BYTES per GPU, held
+ * from the first call on a device until the process ends.  Nothing is
+ * allocated and no memset is issued.
+ *   prob      validated as by mfc_validate (its code is returned on failure);
+ *   q         caller's device state (layout as mfc_step), advanced in place;
+ *   cfl, dt_fixed, t_remaining, dt_dev: as mfc_step;
+ *   flag_dev  caller's device int (required): set to nonzero when c^2 <= 0 or
+ *             a non-finite flux is met, never cleared by the library.
+ * Size limit: 3 * round256(neq * ncell * sizeof(element)) + round256(8 *
+ * max(8192, blocks of the first axis pass)) + 256 bytes must fit
+ * MFC_STATIC_SCRATCH_BYTES (about 1.3M cells for 3D two-fluid FP64, 2.7M in
+ * FP32), else MFC_ERR_SHAPE before any HIP call.  MFC_ERR_HIP if a launch
+ * fails or the array's address cannot be resolved.
+ * Every call on one GPU shares that GPU's array and leaves its contents
+ * behind: calls that overlap on one GPU (other streams, other threads) race.
+ * The call keeps nothing from an earlier call. */
+#define MFC_STATIC_SCRATCH_BYTES (256u << 20)
+int mfc_step_static(const mfc_problem* prob, void* q, double cfl, double dt_fixed, double t_remaining,
+                    double* dt_dev, int* flag_dev, void* hip_stream);
+
 /* Non-uniform grid along `axis` (Sec. 4.2.2): faces is a HOST array of the
  * n[axis] + 1 cell-face coordinates x_{-1/2} .. x_{n-1/2}, strictly
  * increasing and finite (read during the call, not kept); NULL restores the

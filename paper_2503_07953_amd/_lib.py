@@ -63,6 +63,7 @@ SIGNATURES = {
     "mfc_rhs": (_I, [_V, _V, _V, _V]),
     "mfc_max_signal": (_I, [_V, _V, _V, _V]),
     "mfc_step": (_I, [_V, _V, _D, _D, _D, _V, _V]),
+    "mfc_step_static": (_I, [_P, _V, _D, _D, _D, _V, _V, _V]),
     "mfc_conserved_sums": (_I, [_V, _V, _V, _V]),
     "mfc_set_grid": (_I, [_V, _I, _V]),
     "mfc_check": (_I, [_V, _V]),

@@ -867,3 +867,72 @@ int mfc_check(mfc_ctx* c, void* stream) {
 }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Allocation-free step: the same kernels as mfc_step, working in a static
+// device array instead of context scratch.  Every GPU the library runs on
+// holds its own copy of `scratch` until the process ends; host code uses the
+// per-device address returned by hipGetSymbolAddress, never the array's name.
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) unsigned char scratch[MFC_STATIC_SCRATCH_BYTES];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Address of this device's copy of `scratch` (resolved once per device, with
+// that device current).
+hipError_t static_scratch(int dev, unsigned char** out) {
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (!p) return hipErrorInvalidSymbol;
+    g_scratch_ptr[dev] = p;
+  }
+  *out = (unsigned char*)g_scratch_ptr[dev];
+  return hipSuccess;
+}
+
+size_t round256(size_t b) { return (b + 255) & ~size_t(255); }
+
+}  // namespace
+
+extern "C" {
+
+int mfc_step_static(const mfc_problem* p, void* q, double cfl, double dt_fixed, double t_remaining,
+                    double* dt_dev, int* flag_dev, void* stream) {
+  int v = mfc_validate(p);
+  if (v != MFC_OK) return v;
+  const size_t esize = (p->precision == MFC_FP64) ? sizeof(double) : sizeof(float);
+  if (!q || !aligned(q, esize)) return MFC_ERR_ARG;
+  if (!flag_dev || !aligned(flag_dev, sizeof(int))) return MFC_ERR_ARG;
+  if (dt_dev && !aligned(dt_dev, sizeof(double))) return MFC_ERR_ARG;
+  if ((cfl > 0.0) == (dt_fixed > 0.0)) return MFC_ERR_ARG;
+  if (!(cfl < 1e300) || !(dt_fixed < 1e300) || t_remaining != t_remaining) return MFC_ERR_ARG;
+  // scratch layout: accumulator, stage 1, stage 2 (one state each), the
+  // reduction partials, then [smax, dt]; each part starts on 256 bytes
+  const mfc::Params pm = make_params(*p);
+  const size_t state = round256((size_t)mfc_num_eqs(p) * (size_t)pm.ncell * esize);
+  const size_t parts = round256(partial_len(*p) * sizeof(double));
+  const size_t need = 3 * state + parts + 256;
+  if (need > (size_t)MFC_STATIC_SCRATCH_BYTES) return MFC_ERR_SHAPE;
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0) return MFC_ERR_HIP;
+  if (dev >= kMaxDevices) return MFC_ERR_UNSUPPORTED;
+  unsigned char* base = nullptr;
+  if (static_scratch(dev, &base) != hipSuccess) return MFC_ERR_HIP;
+  const StepScratch sc{base, base + state, base + 2 * state, (double*)(base + 3 * state),
+                       (double*)(base + 3 * state + parts), flag_dev};
+  hipStream_t s = (hipStream_t)stream;
+  hipError_t e =
+      (p->precision == MFC_FP64)
+          ? step_t<double>(*p, pm, sc, nullptr, (double*)q, cfl, dt_fixed, t_remaining, dt_dev, s)
+          : step_t<float>(*p, pm, sc, nullptr, (float*)q, cfl, dt_fixed, t_remaining, dt_dev, s);
+  return e == hipSuccess ? MFC_OK : MFC_ERR_HIP;
+}
+
+}  // extern "C"

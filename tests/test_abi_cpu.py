@@ -127,6 +127,25 @@ def test_missing_library_fails_loudly(tmp_path, monkeypatch):
         Solver(1, (8,), 1, (0.1,), (1.4, 1.4), (0.0, 0.0), (1,), (1,))
 
 
+def test_static_step_rejects_before_any_device_call(L):
+    """mfc_step_static checks the problem, the arguments and the scratch size on
+    the host; a problem whose step does not fit the static scratch is refused
+    with MFC_ERR_SHAPE (no HIP call is made, so this runs without a GPU)."""
+    lib = L.load()
+    buf = (ctypes.c_double * 8)()
+    flag = (ctypes.c_int * 1)()
+    q, f = ctypes.cast(buf, ctypes.c_void_p), ctypes.cast(flag, ctypes.c_void_p)
+    big = _prob(L, ndim=3, n=(128, 128, 128), dx=(0.1,) * 3, bc_lo=(1,) * 3, bc_hi=(1,) * 3)
+    assert lib.mfc_step_static(ctypes.byref(big), q, 0.5, 0.0, 0.0, None, f, None) == L.MFC_ERR_SHAPE
+    ok = _prob(L)
+    assert lib.mfc_step_static(ctypes.byref(ok), q, 0.5, 0.1, 0.0, None, f, None) == L.MFC_ERR_ARG
+    assert lib.mfc_step_static(ctypes.byref(ok), q, 0.5, 0.0, 0.0, None, None, None) == L.MFC_ERR_ARG
+    assert lib.mfc_step_static(ctypes.byref(ok), None, 0.5, 0.0, 0.0, None, f, None) == L.MFC_ERR_ARG
+    bad = _prob(L, weno_eps=0.0)
+    assert lib.mfc_step_static(ctypes.byref(bad), q, 0.5, 0.0, 0.0, None, f, None) == L.MFC_ERR_ARG
+    assert lib.mfc_step_static(None, q, 0.5, 0.0, 0.0, None, f, None) == L.MFC_ERR_ARG
+
+
 def test_solver_takes_every_problem_field():
     """Solver.from_case passes the whole problem description (every key of
     Case.problem_kwargs) to the constructor, which must accept each one."""
