@@ -25,7 +25,6 @@ sys.path.insert(0, ROOT)
 
 METRIC = "grind time ns/cell/RK-stage FP64 vs FP32 + %HBM peak; adjoint/forward cost"
 HBM_PEAK_GBS = 8000.0
-FP64_PEAK_TFLOPS = 78.6
 
 
 def log(*a):
@@ -148,41 +147,74 @@ def adjoint_cost(n=256, steps=200, every=20):
 
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_bubble_cloud_256.md")
-TRAFFIC_SOURCES = ("paper_2503_07953_amd/csrc/device.h", "paper_2503_07953_amd/csrc/sweep.hip")
+
+
+def _profile_data(path, tag, ncell):
+    """The JSON line `tag` of a committed profile summary, or None when that
+    summary was taken on different kernel sources (sha256 of the files it
+    lists) or another size."""
+    import hashlib
+    try:
+        line = next(l for l in open(path) if tag in l)
+        data = json.loads(line.split(tag, 1)[1])
+        h = hashlib.sha256()
+        for src in data["sources"]:
+            with open(os.path.join(ROOT, src), "rb") as f:
+                h.update(f.read())
+    except (OSError, StopIteration, ValueError, KeyError):
+        return None
+    if h.hexdigest() != data.get("source_sha256") or data.get("cells") != ncell:
+        return None
+    return data
 
 
 def measured_traffic_bytes(kind, prec, ncell):
     """Calibrated HBM bytes per launch of a sweep pass from the committed
-    FETCH_SIZE / WRITE_SIZE summary, or None when that summary was taken on a
-    different kernel source (sha256 of the forward-kernel files) or size."""
-    import hashlib
-    try:
-        line = next(l for l in open(TRAFFIC_FILE) if "traffic-data:" in l)
-        data = json.loads(line.split("traffic-data:", 1)[1])
-    except (OSError, StopIteration, ValueError):
-        return None
-    h = hashlib.sha256()
-    for src in TRAFFIC_SOURCES:
-        with open(os.path.join(ROOT, src), "rb") as f:
-            h.update(f.read())
-    if h.hexdigest() != data.get("source_sha256") or data.get("cells") != ncell:
-        return None
-    return data.get("bytes_per_launch", {}).get(f"{kind}_{prec}")
+    FETCH_SIZE / WRITE_SIZE summary (None if it is stale)."""
+    data = _profile_data(TRAFFIC_FILE, "traffic-data:", ncell)
+    return data.get("bytes_per_launch", {}).get(f"{kind}_{prec}") if data else None
+
+
+def stage_alg_bytes(neq, esize):
+    """Algorithmic bytes per cell per RK stage: a stage reads q^(k) (and q^n
+    for k >= 2) and writes q^(k+1), on average (8/3) N_eq sizeof(Real)."""
+    return (8.0 / 3.0) * neq * esize
 
 
 def roofline_of(kinds, neq, esize, ndim, ncell, prec=None):
-    """Roofline of the kernel kind with the largest total time: algorithmic
-    bytes per launch over its average launch duration (HIP events)."""
+    """Roofline of the kernel kind with the largest total time.  achieved =
+    the algorithmic bytes of one RK stage per cell ((8/3) N_eq sizeof) times
+    the cells one launch covers, over its average launch duration (HIP events
+    on the launch stream).  The pass's own implementation bytes (what the
+    three-pass design must move in that launch) are reported beside it."""
     dom = max((k for k in kinds if kinds[k][1] > 0), key=lambda k: kinds[k][0])
     avg_ms = kinds[dom][0] / kinds[dom][1]
-    bpc = pass_bytes_per_cell(dom, neq, esize, ndim)
+    bpc = stage_alg_bytes(neq, esize)
     achieved = bpc * ncell / (avg_ms * 1e-3) / 1e9
+    impl = pass_bytes_per_cell(dom, neq, esize, ndim)
     tb = measured_traffic_bytes(dom, prec, ncell) if prec else None
     traffic = round(tb / (avg_ms * 1e-3) / 1e9, 1) if tb else None
     return {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "avg_launch_ms": round(avg_ms, 5),
             "alg_bytes_per_cell": round(bpc, 2),
+            "impl_bytes_per_cell": round(impl, 2),
+            "impl_frac": round(impl * ncell / (avg_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
             "traffic_bytes_per_cell": round(tb / ncell, 1) if tb else None}
+
+
+VALU_FILE = os.path.join(ROOT, "profiles", "valu_sweep_bubble_cloud_256_fp64.md")
+# FP64 vector rate of the chip: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz
+# lane-operations per second (78.6 TFLOP/s counts an FMA as two flops); the
+# same SIMDs issue 614.4 G wave64 instructions per second (4 cycles each).
+FP64_LANE_INSTR_PER_S = 256 * 4 * 16 * 2.4e9
+WAVE_INSTR_PER_S = 256 * 4 * 2.4e9 / 4
+
+
+def measured_valu(kind, ncell):
+    """VALU wave-instructions per launch of a sweep pass (counter summary;
+    None if it is stale)."""
+    data = _profile_data(VALU_FILE, "valu-data:", ncell)
+    return data.get("valu_wave_instr_per_launch", {}).get(kind) if data else None
 
 
 def field_group_errors(a, b, nf, ndim):
@@ -354,14 +386,26 @@ def main():
     grind = ms_step * 1e6 / (ncell * 3)
     log(f"fp64: {ms_step:.3f} ms/step, {grind:.4f} ns/cell/stage, kinds {kinds}")
 
-    # dominant kernel roofline
+    # dominant kernel roofline: HBM on algorithmic bytes, the FP64 vector
+    # units on algorithmic operations and (counters) on executed instructions,
+    # and the attainable fraction: the larger of the two floors over the time
     roofline = roofline_of(kinds, neq, 8, case.ndim, ncell, "fp64")
     dom, avg_ms = roofline["kernel"], roofline["avg_launch_ms"]
-    flops_cell = FLOPS_PASS_3D2F + (FLOPS_STAGE_UPDATE if dom == "pass_z" else 0)
+    flops_cell = FLOPS_PASS_3D2F + (FLOPS_STAGE_UPDATE if dom == "pass_x" else 0)
     tflops = flops_cell * ncell / (avg_ms * 1e-3) / 1e12
     roofline["fp64_tflops_alg"] = round(tflops, 3)
-    roofline["fp64_frac_alg"] = round(tflops / FP64_PEAK_TFLOPS, 4)
-    stage_bytes = (8.0 / 3.0) * neq * 8  # per cell-stage, ideal fused path
+    roofline["fp64_frac_alg"] = round(flops_cell * ncell / (avg_ms * 1e-3) / FP64_LANE_INSTR_PER_S, 4)
+    t_valu_floor = flops_cell * ncell / FP64_LANE_INSTR_PER_S
+    t_hbm_floor = stage_alg_bytes(neq, 8) * ncell / (HBM_PEAK_GBS * 1e9)
+    roofline["attainable_frac"] = round(max(t_valu_floor, t_hbm_floor) / (avg_ms * 1e-3), 4)
+    vi = measured_valu(dom, ncell)
+    roofline["valu_issue_frac_counters"] = round(vi / (avg_ms * 1e-3) / WAVE_INSTR_PER_S, 4) if vi else None
+    stage_bytes = stage_alg_bytes(neq, 8)  # per cell-stage, ideal fused path
+    # whole stage: algorithmic operations of the three passes and the update
+    stage_ms = ms_step / 3.0
+    stage_ops = 3 * FLOPS_PASS_3D2F + FLOPS_STAGE_UPDATE
+    stage_attainable = max(stage_ops * ncell / FP64_LANE_INSTR_PER_S,
+                           stage_bytes * ncell / (HBM_PEAK_GBS * 1e9)) / (stage_ms * 1e-3)
 
     # ---------------- FP32 form ----------------
     fp32 = None
@@ -389,7 +433,9 @@ def main():
                  "bubble_cloud_weno_z": variant_grind(case, 1, args.steps, args.warmup),
                  "bubble_cloud_teno5": variant_grind(case, 2, args.steps, args.warmup),
                  "bubble_cloud_weno_m": variant_grind(case, 3, args.steps, args.warmup),
-                 "bubble_cloud_hll": variant_grind(case, 0, args.steps, args.warmup, riemann=1),
+                 # the 256^3 bubble cloud breaks down under HLL at step index 26 (both the
+                 # oracle and the library): this leg runs a fixed 3 + 20 steps
+                 "bubble_cloud_hll": variant_grind(case, 0, 20, 3, riemann=1),
                  "bubble_cloud_low_mach": variant_grind(case, 0, args.steps, args.warmup, low_mach=1),
                  "paper_benchmark_shape": paper_shape_grind(args.steps, args.warmup)}
         log(f"extra: {extra}")
@@ -415,9 +461,32 @@ def main():
                 model = next(l.split(":", 1)[1].strip() for l in f if l.startswith("model name"))
         except (OSError, StopIteration):
             pass
+        del qh, O
+        # the shock-cylinder configuration (512^2, 2D) on all threads: 20 steps
+        c1 = W.shock_cylinder(512)
+        O1 = oracle.Oracle(c1)
+        q1 = O1.prim_to_cons(c1.w)
+        t0 = time.time()
+        O1.run(q1, 20, cfl=c1.cfl)
+        t_c1 = time.time() - t0
+        del q1, O1
+        # one thread: 1 SSP-RK3 step of the same bubble-cloud generator at 64^3
+        # (the per-cell work does not depend on the grid size)
+        c64 = W.bubble_cloud(64, nbub=8, slab=8)
+        O64 = oracle.Oracle(c64)
+        q64 = O64.prim_to_cons(c64.w)
+        oracle.set_num_threads(1)
+        t0 = time.time()
+        O64.step(q64, cfl=c64.cfl)
+        t_1 = time.time() - t0
+        oracle.set_num_threads(threads)
         cpu = {"value": round(t_cpu * 1e9 / (ncell * 3), 3), "unit": "ns/cell/RK-stage", "cores": threads,
                "kind": "oracle", "sample": f"1 SSP-RK3 step (3 RHS evaluations) of the {args.n}^3 bubble cloud, "
-                                           f"{t_cpu:.1f} s wall on {threads} OpenMP threads ({model})"}
+                                           f"{t_cpu:.1f} s wall on {threads} OpenMP threads ({model})",
+               "shock_cylinder_512": {"value": round(t_c1 * 1e9 / (c1.ncell * 3 * 20), 3), "cores": threads,
+                                      "sample": f"20 SSP-RK3 steps of the 512^2 shock-cylinder, {t_c1:.1f} s"},
+               "single_thread": {"value": round(t_1 * 1e9 / (c64.ncell * 3), 3), "cores": 1,
+                                 "sample": f"1 SSP-RK3 step of the 64^3 bubble cloud (8 bubbles), {t_1:.1f} s"}}
         log(f"cpu oracle: {cpu}")
 
     out = {
@@ -433,6 +502,7 @@ def main():
                           round(max(reps) / args.steps * 1e6 / (ncell * 3), 5)],
         "grind_ns_per_cell_pde_rhs": round(grind / neq, 6),
         "hbm_frac_stage_alg": round(stage_bytes / (grind * 1e-9) / 1e9 / HBM_PEAK_GBS, 4),
+        "attainable_frac_stage": round(stage_attainable, 4),
         "kernel_ms": {k: [round(v[0], 4), v[1]] for k, v in kinds.items()},
         "roofline": roofline,
         "fp32_form": fp32,

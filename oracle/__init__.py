@@ -99,6 +99,7 @@ def lib():
             "orc_conserved_sums": (ctypes.c_int, [P, dp, dp]),
             "orc_abi_version": (ctypes.c_int, []),
             "orc_num_threads": (ctypes.c_int, []),
+            "orc_set_num_threads": (None, [ctypes.c_int]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -303,6 +304,11 @@ def weno5_nu(f, h, eps=1e-6):
 
 def num_threads() -> int:
     return lib().orc_num_threads()
+
+
+def set_num_threads(n: int) -> None:
+    """OpenMP threads of the oracle's parallel loops from now on."""
+    lib().orc_set_num_threads(int(n))
 
 
 def weno5_js_left(f, eps=1e-6):

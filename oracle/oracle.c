@@ -1023,6 +1023,15 @@ int orc_conserved_sums(const orc_problem* P, const double* q, double* sums) {
 
 int orc_abi_version(void) { return 1; }
 
+/* Set the OpenMP thread count of the parallel loops (n >= 1). */
+void orc_set_num_threads(int n) {
+#ifdef _OPENMP
+  if (n >= 1) omp_set_num_threads(n);
+#else
+  (void)n;
+#endif
+}
+
 /* OpenMP threads the parallel loops use. */
 int orc_num_threads(void) {
 #ifdef _OPENMP
