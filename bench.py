@@ -296,24 +296,34 @@ def paper_shape_grind(steps=20, warmup=3):
     return out
 
 
-def variant_grind(case, variant, steps=20, warmup=3, riemann=0, low_mach=0):
+def variant_grind(case, variant, steps=20, warmup=3, riemann=0, low_mach=0, model=0, faces=None):
     """The same bubble cloud with the WENO5-Z (1) or TENO5 (2) weights of
-    Sec. 4.2.2, the mapped WENO5-M weights (3) of Sec. 3.2.1, or (riemann=1)
-    the HLL face solver of Sec. 3.2.2: FP64 and FP32 grind."""
+    Sec. 4.2.2, the mapped WENO5-M weights (3) of Sec. 3.2.1, (riemann=1) the
+    HLL face solver of Sec. 3.2.2, a low-Mach treatment (1 Thornber, 2 APC),
+    Kapila's K (model=1) or a non-uniform grid (faces): FP64 and FP32 grind.
+    A step that meets c^2 <= 0 is reported instead of a time."""
     import dataclasses
 
+    from paper_2503_07953_amd import _lib as L
     from paper_2503_07953_amd.solver import Solver
-    cz = dataclasses.replace(case, weno_variant=variant, riemann=riemann, low_mach=low_mach)
+    cz = dataclasses.replace(case, weno_variant=variant, riemann=riemann, low_mach=low_mach, model=model,
+                             faces=faces)
     out = {}
     for prec in ("fp64", "fp32"):
         S = Solver.from_case(cz, precision=prec)
         reps = []
-        for _ in range(3):
-            # every repeat from the initial state: warmup + steps CFL steps
-            q = S.prim_to_cons(S.to_device(cz.w))
-            ms, _, _ = time_steps(S, q, steps, warmup, cz.cfl, kernel_steps=0, repeats=1)
-            reps.append(ms)
-            del q
+        try:
+            for _ in range(3):
+                # every repeat from the initial state: warmup + steps CFL steps
+                q = S.prim_to_cons(S.to_device(cz.w))
+                ms, _, _ = time_steps(S, q, steps, warmup, cz.cfl, kernel_steps=0, repeats=1)
+                reps.append(ms)
+                del q
+        except L.MfcError as e:
+            out[f"{prec}_ns_per_cell_stage"] = None
+            out[f"{prec}_error"] = str(e)
+            del S
+            continue
         ms = sorted(reps)[1]
         out[f"{prec}_ns_per_cell_stage"] = round(ms / steps * 1e6 / (cz.ncell * 3), 5)
         del S
@@ -437,6 +447,12 @@ def main():
                  # oracle and the library): this leg runs a fixed 3 + 20 steps
                  "bubble_cloud_hll": variant_grind(case, 0, 20, 3, riemann=1),
                  "bubble_cloud_low_mach": variant_grind(case, 0, args.steps, args.warmup, low_mach=1),
+                 "bubble_cloud_apc": variant_grind(case, 0, args.steps, args.warmup, low_mach=2),
+                 "bubble_cloud_kapila": variant_grind(case, 0, args.steps, args.warmup, model=1),
+                 # centre-clustered grid, width ratio 2 along every axis
+                 "bubble_cloud_stretched": variant_grind(
+                     case, 0, args.steps, args.warmup,
+                     faces=tuple(W.stretched_faces(args.n, 1.0, -1.0 / 3.0) for _ in range(3))),
                  "paper_benchmark_shape": paper_shape_grind(args.steps, args.warmup)}
         log(f"extra: {extra}")
     slab = None

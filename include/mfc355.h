@@ -227,9 +227,10 @@ int mfc_step_static(const mfc_problem* prob, void* q, double cfl, double dt_fixe
  * (wrap, nearest cell or mirror image).  The coefficients are formed on the
  * host in double and kept on the device in the context (allocated at the
  * first call, synchronous copy).
- * WENO5-JS problems only (MFC_ERR_UNSUPPORTED otherwise); while any axis is
- * non-uniform the RHS and step adjoints return MFC_ERR_UNSUPPORTED, and
- * mfc_step_static (no context) always uses the uniform spacing.
+ * WENO5-JS problems only (MFC_ERR_UNSUPPORTED otherwise); the adjoint entry
+ * points follow the grid (their hand-written VJP of the tabulated
+ * reconstruction and per-cell widths); mfc_step_static (no context) always
+ * uses the uniform spacing.
  * MFC_ERR_ARG for a bad axis or face array. */
 int mfc_set_grid(mfc_ctx* ctx, int axis, const double* faces);
 

@@ -16,10 +16,10 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libmfc355.so")
 # the axis passes and the RHS adjoint are split per reconstruction variant
-# (sweep_wv*.hip, vjp_wv*.hip; sweep_wv4: non-uniform grids) so that they
+# (sweep_wv*.hip, vjp_wv*.hip; variant 4: non-uniform grids) so that they
 # compile in parallel
 SOURCES = ["sweep_wv0.hip", "sweep_wv1.hip", "sweep_wv2.hip", "sweep_wv3.hip", "sweep_wv4.hip",
-           "vjp_wv0.hip", "vjp_wv1.hip", "vjp_wv2.hip", "vjp_wv3.hip",
+           "vjp_wv0.hip", "vjp_wv1.hip", "vjp_wv2.hip", "vjp_wv3.hip", "vjp_wv4.hip",
            "api.hip", "sweep.hip", "reduce.hip", "vjp.hip"]
 
 HIPCC = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"

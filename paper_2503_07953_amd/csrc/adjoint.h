@@ -320,6 +320,72 @@ __host__ __device__ __forceinline__ void weno5_js_vjp(const double* f, double ep
 }
 
 // ---------------------------------------------------------------------------
+// Adjoint of the non-uniform WENO5-JS of one centre (weno5_nu): with
+// cotangents gR of the value at the right face and gL of the value at the
+// left face, accumulates g[0..4] of the five cell values.  Forward: per
+// candidate r, m0' = mu0 (D_r, D_{r+1}), m1, m2 linear in the two differences,
+// values f_2 + m0' + m2/4 +- m1/2, indicator beta_r = m1^2 + (13/3) m2^2,
+// weights d_r/(eps + beta_r)^2 normalized per face.  Reverse: the candidate
+// cotangents are g omega_r, and beta_r collects -2/(eps + beta_r) times
+// g omega_r (q_r - (y - f_2)) from each face.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void weno_nu_vjp(double a, double b, double c, double d, double e, double eps,
+                                            const double* cf, long long st, double gR, double gL, double* g) {
+  const double D[4] = {b - a, c - b, d - c, e - d};
+  double qr[3], ql[3], beta[3], m1[3], m2[3];
+#pragma unroll
+  for (int r = 0; r < 3; ++r) {
+    const double da = D[r], db = D[r + 1];
+    const double mu0 = cf[(NU_MU0 + 2 * r) * st] * da + cf[(NU_MU0 + 2 * r + 1) * st] * db;
+    m1[r] = cf[(NU_M1 + 2 * r) * st] * da + cf[(NU_M1 + 2 * r + 1) * st] * db;
+    m2[r] = cf[(NU_M2 + 2 * r) * st] * da + cf[(NU_M2 + 2 * r + 1) * st] * db;
+    const double even = mu0 + 0.25 * m2[r];
+    qr[r] = even + 0.5 * m1[r];
+    ql[r] = even - 0.5 * m1[r];
+    beta[r] = m1[r] * m1[r] + (13.0 / 3.0) * (m2[r] * m2[r]);
+  }
+  const double s0 = eps + beta[0], s1 = eps + beta[1], s2 = eps + beta[2];
+  const double t0 = s0 * s0, t1 = s1 * s1, t2 = s2 * s2;
+  const double p[3] = {t1 * t2, t0 * t2, t0 * t1};
+  double wr[3], wl[3];
+#pragma unroll
+  for (int r = 0; r < 3; ++r) {
+    wr[r] = cf[(NU_DR + r) * st] * p[r];
+    wl[r] = cf[(NU_DL + r) * st] * p[r];
+  }
+  const double sr = wr[0] + wr[1] + wr[2], sl = wl[0] + wl[1] + wl[2];
+  const double inv = fast_rcp(sr * sl);
+  const double isr = sl * inv, isl = sr * inv;
+  double cR = 0.0, cL = 0.0;
+#pragma unroll
+  for (int r = 0; r < 3; ++r) {
+    wr[r] *= isr;
+    wl[r] *= isl;
+    cR += wr[r] * qr[r];
+    cL += wl[r] * ql[r];
+  }
+  const double sv[3] = {s0, s1, s2};
+  double Db[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int r = 0; r < 3; ++r) {
+    const double qrb = gR * wr[r], qlb = gL * wl[r];
+    const double bb = -2.0 * fast_rcp(sv[r]) * (qrb * (qr[r] - cR) + qlb * (ql[r] - cL));
+    const double mu0b = qrb + qlb;
+    const double m1b = 0.5 * (qrb - qlb) + 2.0 * m1[r] * bb;
+    const double m2b = 0.25 * (qrb + qlb) + (26.0 / 3.0) * m2[r] * bb;
+    Db[r] += cf[(NU_MU0 + 2 * r) * st] * mu0b + cf[(NU_M1 + 2 * r) * st] * m1b + cf[(NU_M2 + 2 * r) * st] * m2b;
+    Db[r + 1] += cf[(NU_MU0 + 2 * r + 1) * st] * mu0b + cf[(NU_M1 + 2 * r + 1) * st] * m1b +
+                 cf[(NU_M2 + 2 * r + 1) * st] * m2b;
+  }
+  g[2] += gR + gL;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    g[k + 1] += Db[k];
+    g[k] -= Db[k];
+  }
+}
+
+// ---------------------------------------------------------------------------
 // HLLC adjoint (same readings as hllc()): given Fbar (every row) and ufbar,
 // accumulate WLbar and WRbar.  Double precision.
 // ---------------------------------------------------------------------------

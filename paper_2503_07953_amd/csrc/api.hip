@@ -718,8 +718,6 @@ int mfc_rhs_vjp(mfc_ctx* c, const void* q, const void* rhs_bar, void* q_bar, int
   if (!c) return MFC_ERR_ARG;
   if (int rd = check_device(c)) return rd;
   if (c->prob.precision != MFC_FP64) return fail(c, MFC_ERR_UNSUPPORTED, "adjoint entry points are FP64 only");
-  if (c->pm.nu[0] || c->pm.nu[1] || c->pm.nu[2])
-    return fail(c, MFC_ERR_UNSUPPORTED, "adjoint entry points need a uniform grid");
   int r;
   if ((r = check_array(c, q, "q")) || (r = check_array(c, rhs_bar, "rhs_bar")) || (r = check_array(c, q_bar, "q_bar")))
     return r;
@@ -735,8 +733,6 @@ int mfc_step_vjp(mfc_ctx* c, const void* q_n, double dt, const void* qnp1_bar, v
   if (!c) return MFC_ERR_ARG;
   if (int rd = check_device(c)) return rd;
   if (c->prob.precision != MFC_FP64) return fail(c, MFC_ERR_UNSUPPORTED, "adjoint entry points are FP64 only");
-  if (c->pm.nu[0] || c->pm.nu[1] || c->pm.nu[2])
-    return fail(c, MFC_ERR_UNSUPPORTED, "adjoint entry points need a uniform grid");
   int r;
   if ((r = check_array(c, q_n, "q_n")) || (r = check_array(c, qnp1_bar, "qnp1_bar")) ||
       (r = check_array(c, qn_bar, "qn_bar")))
@@ -763,8 +759,6 @@ int mfc_step_save_stages(mfc_ctx* c, void* q, double dt, void* q1, void* q2, voi
   if (!c) return MFC_ERR_ARG;
   if (int rd = check_device(c)) return rd;
   if (c->prob.precision != MFC_FP64) return fail(c, MFC_ERR_UNSUPPORTED, "adjoint entry points are FP64 only");
-  if (c->pm.nu[0] || c->pm.nu[1] || c->pm.nu[2])
-    return fail(c, MFC_ERR_UNSUPPORTED, "adjoint entry points need a uniform grid");
   int r;
   if ((r = check_array(c, q, "q")) || (r = check_array(c, q1, "q1")) || (r = check_array(c, q2, "q2"))) return r;
   if (!(dt > 0.0) || !(dt < 1e300)) return fail(c, MFC_ERR_ARG, "dt must be positive and finite");
@@ -790,8 +784,6 @@ int mfc_step_vjp_stages(mfc_ctx* c, const void* q_n, const void* q1, const void*
   if (!c) return MFC_ERR_ARG;
   if (int rd = check_device(c)) return rd;
   if (c->prob.precision != MFC_FP64) return fail(c, MFC_ERR_UNSUPPORTED, "adjoint entry points are FP64 only");
-  if (c->pm.nu[0] || c->pm.nu[1] || c->pm.nu[2])
-    return fail(c, MFC_ERR_UNSUPPORTED, "adjoint entry points need a uniform grid");
   int r;
   if ((r = check_array(c, q_n, "q_n")) || (r = check_array(c, q1, "q1")) || (r = check_array(c, q2, "q2")) ||
       (r = check_array(c, qnp1_bar, "qnp1_bar")) || (r = check_array(c, qn_bar, "qn_bar")))

@@ -9,9 +9,12 @@ MFC_EXTERN_VJP(0)
 MFC_EXTERN_VJP(1)
 MFC_EXTERN_VJP(2)
 MFC_EXTERN_VJP(3)
+MFC_EXTERN_VJP(4)
 
 hipError_t launch_rhs_vjp(int nf, int ndim, const Params& pm, const double* q, const double* rbar, double* qbar,
                           const VjpScratch& sc, bool accumulate, hipStream_t s, PassTimer* tm) {
+  if (pm.nu[0] || pm.nu[1] || pm.nu[2])
+    return launch_rhs_vjp_wv<kWvNonUniform>(nf, ndim, pm, q, rbar, qbar, sc, accumulate, s, tm);
   switch (pm.weno_variant) {
     case 1: return launch_rhs_vjp_wv<1>(nf, ndim, pm, q, rbar, qbar, sc, accumulate, s, tm);
     case 2: return launch_rhs_vjp_wv<2>(nf, ndim, pm, q, rbar, qbar, sc, accumulate, s, tm);

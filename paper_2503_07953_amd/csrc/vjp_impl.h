@@ -171,7 +171,9 @@ __device__ __forceinline__ void face_tile(const Params pm, const double* __restr
 
   // face cotangents: Fbar = (rbar_f - rbar_{f-1})/dx over interior cells, and
   // ufbar from the alpha source of the two cells sharing the face
-  const double inv_dx = pm.inv_dx[DIR];
+  // 1/h of the two cells sharing the face (tabulated on a non-uniform grid)
+  const double ih0 = (WV == kWvNonUniform) ? inv_width(pm, DIR, f - 1) : pm.inv_dx[DIR];
+  const double ih1 = (WV == kWvNonUniform) ? inv_width(pm, DIR, f) : pm.inv_dx[DIR];
   const bool in0 = f - 1 >= 0, in1 = f < nd;
   const long long c0 = cell_at<DIR>(in0 ? f - 1 : 0, i, j, k, nx, ny);
   const long long c1 = cell_at<DIR>(in1 ? f : 0, i, j, k, nx, ny);
@@ -188,20 +190,32 @@ __device__ __forceinline__ void face_tile(const Params pm, const double* __restr
   for (int v = 0; v < NEQ; ++v) {
     const double r0 = in0 ? rbar[v * nc + c0] : 0.0;
     const double r1 = in1 ? rbar[v * nc + c1] : 0.0;
-    Fb[v] = inv_dx * (r1 - r0);
+    Fb[v] = ih1 * r1 - ih0 * r0;
     if constexpr (NF == 2) {
-      if (v == R::ALPHA) ufb += (Ws(2, v) + K0) * r0 - (Ws(3, v) + K1) * r1;
-      if (v == R::ALPHA + 1) ufb += (Ws(2, v) - K0) * r0 - (Ws(3, v) - K1) * r1;
+      if (v == R::ALPHA) ufb += ih0 * ((Ws(2, v) + K0) * r0) - ih1 * ((Ws(3, v) + K1) * r1);
+      if (v == R::ALPHA + 1) ufb += ih0 * ((Ws(2, v) - K0) * r0) - ih1 * ((Ws(3, v) - K1) * r1);
     }
   }
-  ufb *= inv_dx;
 
+  // non-uniform grid: table entries of the centres f - 1 and f along the axis
+  const long long nst = (long long)nd + 6;
+  const double* cfa = nullptr;
+  const double* cfb = nullptr;
+  if constexpr (WV == kWvNonUniform) {
+    cfa = pm.nu[DIR] + (f - 1 + 3);
+    cfb = pm.nu[DIR] + (f + 3);
+  }
   double WL[NEQ], WR[NEQ];
 #pragma unroll
   for (int v = 0; v < NEQ; ++v) {
     double l, r, t;
-    weno5<WV>(Ws(0, v), Ws(1, v), Ws(2, v), Ws(3, v), Ws(4, v), pm.eps, l, t);
-    weno5<WV>(Ws(1, v), Ws(2, v), Ws(3, v), Ws(4, v), Ws(5, v), pm.eps, t, r);
+    if constexpr (WV == kWvNonUniform) {
+      weno5_nu(Ws(0, v), Ws(1, v), Ws(2, v), Ws(3, v), Ws(4, v), pm.eps, cfa, nst, l, t);
+      weno5_nu(Ws(1, v), Ws(2, v), Ws(3, v), Ws(4, v), Ws(5, v), pm.eps, cfb, nst, t, r);
+    } else {
+      weno5<WV>(Ws(0, v), Ws(1, v), Ws(2, v), Ws(3, v), Ws(4, v), pm.eps, l, t);
+      weno5<WV>(Ws(1, v), Ws(2, v), Ws(3, v), Ws(4, v), Ws(5, v), pm.eps, t, r);
+    }
     WL[v] = l;
     WR[v] = r;
   }
@@ -228,7 +242,16 @@ __device__ __forceinline__ void face_tile(const Params pm, const double* __restr
   for (int v = 0; v < NEQ; ++v) {
     double g[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     double gr[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-    if constexpr (WV == 1) {
+    if constexpr (WV == kWvNonUniform) {
+      // centre f - 1 gives the left state (its right-face value), centre f
+      // the right state (its left-face value); gr holds centre f's stencil
+      // in natural order, folded below as the reversed uniform stencils are
+      weno_nu_vjp(Ws(0, v), Ws(1, v), Ws(2, v), Ws(3, v), Ws(4, v), pm.eps, cfa, nst, WLb[v], 0.0, g);
+      double gb[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+      weno_nu_vjp(Ws(1, v), Ws(2, v), Ws(3, v), Ws(4, v), Ws(5, v), pm.eps, cfb, nst, 0.0, WRb[v], gb);
+#pragma unroll
+      for (int k = 0; k < 5; ++k) gr[4 - k] = gb[k];
+    } else if constexpr (WV == 1) {
       weno_z_left_vjp(Ws(0, v), Ws(1, v), Ws(2, v), Ws(3, v), Ws(4, v), pm.eps, WLb[v], g);
       weno_z_left_vjp(Ws(5, v), Ws(4, v), Ws(3, v), Ws(2, v), Ws(1, v), pm.eps, WRb[v], gr);
     } else if constexpr (WV == 2) {
@@ -365,7 +388,7 @@ __device__ __forceinline__ void gather_axis(const Params& pm, const double* __re
     int f1[3] = {i, j, k};
     f1[DIR] = p + 1;
     const long long fid1 = ((long long)f1[2] * fg.fy + f1[1]) * fg.fx + f1[0];
-    div += pm.inv_dx[DIR] * (UF[fid1] - UF[fid0]);
+    div += inv_width(pm, DIR, p) * (UF[fid1] - UF[fid0]);
   }
 }
 
