@@ -145,6 +145,33 @@ __host__ __device__ __forceinline__ void cons_to_prim(const Params& pm, const do
   }
 }
 
+// Primitive -> conservative for one cell, in double: rho u = rho * u,
+// rho E = Gamma p + Pi + rho |u|^2/2.
+template <int NF, int D>
+__host__ __device__ __forceinline__ void prim_to_cons(const Params& pm, const double* W, double* U) {
+  using R = Rows<NF, D>;
+  double rho = W[0];
+  if constexpr (NF == 2) rho = W[0] + W[1];
+  double usq = 0.0;
+#pragma unroll
+  for (int d = 0; d < D; ++d) {
+    U[R::MOM + d] = rho * W[R::MOM + d];
+    usq += W[R::MOM + d] * W[R::MOM + d];
+  }
+  double Gam, Pi;
+  if constexpr (NF == 2)
+    mixture<NF, double>(pm, W[R::ALPHA], W[R::ALPHA + 1], Gam, Pi);
+  else
+    mixture<NF, double>(pm, 1.0, 0.0, Gam, Pi);
+  U[R::E] = Gam * W[R::E] + Pi + 0.5 * rho * usq;
+#pragma unroll
+  for (int i = 0; i < NF; ++i) U[i] = W[i];
+  if constexpr (NF == 2) {
+    U[R::ALPHA] = W[R::ALPHA];
+    U[R::ALPHA + 1] = W[R::ALPHA + 1];
+  }
+}
+
 // Squared mixture sound speed, the mixture read as one stiffened gas with
 // gamma_m = 1 + 1/Gamma, pi_m = Pi/(Gamma + 1): c^2 = ((Gamma+1) p + Pi)/(Gamma rho).
 __host__ __device__ __forceinline__ double sound_speed_sq(double rho, double p, double Gam, double Pi) {

@@ -188,26 +188,7 @@ __global__ __launch_bounds__(256) void convert_kernel(Params pm, const Real* __r
 #pragma unroll
     for (int v = 0; v < NEQ; ++v) X[v] = double(in[v * nc + c]);
     if constexpr (TO_CONS) {
-      double rho = X[0];
-      if constexpr (NF == 2) rho = X[0] + X[1];
-      double usq = 0.0;
-#pragma unroll
-      for (int d = 0; d < D; ++d) {
-        Y[R::MOM + d] = rho * X[R::MOM + d];
-        usq += X[R::MOM + d] * X[R::MOM + d];
-      }
-      double Gam, Pi;
-      if constexpr (NF == 2)
-        mixture<NF, double>(pm, X[R::ALPHA], X[R::ALPHA + 1], Gam, Pi);
-      else
-        mixture<NF, double>(pm, 1.0, 0.0, Gam, Pi);
-      Y[R::E] = Gam * X[R::E] + Pi + 0.5 * rho * usq;
-#pragma unroll
-      for (int i = 0; i < NF; ++i) Y[i] = X[i];
-      if constexpr (NF == 2) {
-        Y[R::ALPHA] = X[R::ALPHA];
-        Y[R::ALPHA + 1] = X[R::ALPHA + 1];
-      }
+      prim_to_cons<NF, D>(pm, X, Y);
     } else {
       cons_to_prim<NF, D>(pm, X, Y);
     }

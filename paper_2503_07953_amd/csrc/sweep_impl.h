@@ -19,7 +19,10 @@
 //       stage states into the next stage state.
 // Reconstructed states, fluxes and face velocities live only in registers
 // and LDS; HBM sees one read of the stage state (plus halos), the RHS
-// accumulator round trip and the stage combination.
+// accumulator round trip and the stage combination.  In the x pass the
+// values of neighbouring centres move between adjacent lanes (DPP) instead
+// of through LDS, and the stage update takes the centre's state from the
+// primitives still in LDS rather than reading q_k a second time.
 //
 // Tile shapes (wave64): along x the centres of a tile are the 64 lanes of a
 // wave, one wave per x-row, 4 rows per block; along y and z, 32 x-lanes by 16
@@ -48,6 +51,23 @@ __device__ __forceinline__ void st_acc(Real v, Real* p) {
     __builtin_nontemporal_store(v, p);
   else
     *p = v;
+}
+
+// Exchange between adjacent lanes of a wave (DPP wave_shr:1 / wave_shl:1):
+// lane i receives lane i-1's value (kFromPrev) or lane i+1's (kFromNext); the
+// lane at the end with no source receives 0.  Called with every lane active.
+constexpr int kFromPrev = 0x138;
+constexpr int kFromNext = 0x130;
+template <int CTRL>
+__device__ __forceinline__ double lane_shift(double x) {
+  const long long bits = __double_as_longlong(x);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(bits & 0xffffffffll), CTRL, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(bits >> 32), CTRL, 0xf, 0xf, false);
+  return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+template <int CTRL>
+__device__ __forceinline__ float lane_shift(float x) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, 0xf, 0xf, false));
 }
 
 template <int DIR, int D, typename Real>
@@ -85,6 +105,14 @@ __global__ __launch_bounds__((Tile<DIR, D, Real>::NT)) void sweep_kernel(Params 
   using TL = Tile<DIR, D, Real>;
   constexpr int NEQ = R::NEQ;
   __shared__ Real sh[(NEQ + 1) * TL::SA * TL::TB];
+  // x pass: a tile row is one wave of 64 centres, so the neighbours a - 1 and
+  // a + 1 of centre a are the adjacent lanes.  The biased values and the
+  // fluxes move between lanes by DPP and the LDS keeps the primitives to the
+  // end (no barrier after the load); the double stage update takes the
+  // centre's conservative values from them instead of a second read of q_k.
+  constexpr bool kLaneX = DIR == 0;
+  static_assert(!kLaneX || TL::TA == 64, "an x tile row is one wave");
+  constexpr bool kCentreFromLds = kLaneX && sizeof(Real) == 8 && (MODE & MODE_STEP) != 0;
 
   const int nx = pm.n[0], ny = pm.n[1];
   const int nd = pm.n[DIR];
@@ -232,6 +260,7 @@ __global__ __launch_bounds__((Tile<DIR, D, Real>::NT)) void sweep_kernel(Params 
   }
 
   // ---- (b) WENO5-JS at centre c -----------------------------------------------
+  // (lanes past the grid leave them unset: no face reads them)
   Real WLc[NEQ], WRc[NEQ];  // value at c+1/2 (left-biased) and at c-1/2 (right-biased)
   // volume fractions of the centre cell for the alpha source; with RS_KAPILA
   // they carry Kapila's K of the cell, (alpha_1 + K, alpha_2 - K)
@@ -270,47 +299,87 @@ __global__ __launch_bounds__((Tile<DIR, D, Real>::NT)) void sweep_kernel(Params 
       }
     }
   }
-  __syncthreads();
-  if (centre_ok) {
+  if constexpr (!kLaneX) {
+    __syncthreads();
+    if (centre_ok) {
 #pragma unroll
-    for (int v = 0; v < NEQ; ++v) sh[lds_index<DIR, D, Real>(v, a, b)] = WLc[v];
+      for (int v = 0; v < NEQ; ++v) sh[lds_index<DIR, D, Real>(v, a, b)] = WLc[v];
+    }
+    __syncthreads();
   }
-  __syncthreads();
 
   // ---- (c) HLLC at the face c-1/2 between centres c-1 (left) and c (right) ----
   Real F[NEQ];
   Real uf = Real(0);
   const bool face_ok = centre_ok && a >= 1;
-  if (face_ok) {
-    Real WL[NEQ];
+  Real WL[NEQ];
+  if constexpr (kLaneX) {
 #pragma unroll
-    for (int v = 0; v < NEQ; ++v) WL[v] = sh[lds_index<DIR, D, Real>(v, a - 1, b)];
+    for (int v = 0; v < NEQ; ++v) WL[v] = lane_shift<kFromPrev>(WLc[v]);
+  }
+  if (face_ok) {
+    if constexpr (!kLaneX) {
+#pragma unroll
+      for (int v = 0; v < NEQ; ++v) WL[v] = sh[lds_index<DIR, D, Real>(v, a - 1, b)];
+    }
     // RS: face solver and low-Mach treatment (RS_HLL, RS_THORNBER, RS_APC),
     // compile-time so that none costs registers where it is off
     if constexpr ((RS & RS_THORNBER) != 0) thornber<NF, D, DIR, Real>(pm, WL, WRc);
     const bool bad = riemann<RS, NF, D, DIR, Real>(pm, WL, WRc, F, uf);
     if (bad) atomicOr(flag, 1);
   }
-  __syncthreads();
-  if (face_ok) {
+  // the face c+1/2, high side of the output cell c (x pass: each flux row
+  // moves from lane a + 1 where it is used, below, with every lane active)
+  Real uhi = Real(0);
+  if constexpr (kLaneX) {
+    uhi = lane_shift<kFromNext>(uf);
+  } else {
+    __syncthreads();
+    if (face_ok) {
 #pragma unroll
-    for (int v = 0; v < NEQ; ++v) sh[lds_index<DIR, D, Real>(v, a, b)] = F[v];
-    sh[lds_index<DIR, D, Real>(NEQ, a, b)] = uf;
+      for (int v = 0; v < NEQ; ++v) sh[lds_index<DIR, D, Real>(v, a, b)] = F[v];
+      sh[lds_index<DIR, D, Real>(NEQ, a, b)] = uf;
+    }
+    __syncthreads();
   }
-  __syncthreads();
 
   // ---- (d) axis contribution for output cell c --------------------------------
-  if (!(line_ok && a >= 1 && a <= TL::TA - 2 && c >= 0 && c < nd)) return;
+  const bool out_ok = line_ok && a >= 1 && a <= TL::TA - 2 && c >= 0 && c < nd;
+  if constexpr (!kLaneX) {
+    if (!out_ok) return;
+  }
   if constexpr (DIR == 0) ox = c;
   else if constexpr (DIR == 1) oy = c;
   else oz = c;
   const long long cell = ((long long)oz * ny + oy) * nx + ox;
   const Real inv_dx = Real((WV == kWvNonUniform) ? inv_width(pm, DIR, c) : pm.inv_dx[DIR]);
-  const Real uhi = sh[lds_index<DIR, D, Real>(NEQ, a + 1, b)];
+  if constexpr (!kLaneX) uhi = sh[lds_index<DIR, D, Real>(NEQ, a + 1, b)];
   const Real div = inv_dx * (uhi - uf);
+  // the centre's conservative values from its primitives (slot a + 2), each
+  // where it is used: the partial densities and volume fractions are the
+  // stored rows, momentum is rho u and the energy Gamma p + Pi + rho |u|^2/2
+  auto centre_cons = [&](int v) -> double {
+    auto w = [&](int r) { return double(sh[lds_index<DIR, D, Real>(r, a + 2, b)]); };
+    if (v == R::E) {
+      double Wc[NEQ], Uc[NEQ];
+#pragma unroll
+      for (int r = 0; r < NEQ; ++r) Wc[r] = w(r);
+      prim_to_cons<NF, D>(pm, Wc, Uc);
+      return Uc[R::E];
+    }
+    if (v >= R::MOM && v < R::MOM + D) return ((NF == 2) ? w(0) + w(1) : w(0)) * w(v);
+    return w(v);
+  };
 #pragma unroll
   for (int v = 0; v < NEQ; ++v) {
-    Real Dv = inv_dx * (F[v] - sh[lds_index<DIR, D, Real>(v, a + 1, b)]);
+    Real fhi;
+    if constexpr (kLaneX) {
+      fhi = lane_shift<kFromNext>(F[v]);
+      if (!out_ok) continue;
+    } else {
+      fhi = sh[lds_index<DIR, D, Real>(v, a + 1, b)];
+    }
+    Real Dv = inv_dx * (F[v] - fhi);
     if constexpr (NF == 2) {
       if (v == R::ALPHA) Dv = Dv + alpha_cell[0] * div;
       if (v == R::ALPHA + 1) Dv = Dv + alpha_cell[1] * div;
@@ -324,7 +393,13 @@ __global__ __launch_bounds__((Tile<DIR, D, Real>::NT)) void sweep_kernel(Params 
     if constexpr (MODE & MODE_STEP) {
       // SSP-RK3, Shu-Osher form (Sec. 3.4), combined in double
       const double dt = st.dt_ptr ? *st.dt_ptr : st.dt;
-      const double qs = double(qk[e]) + dt * double(r);
+      double uk;
+      if constexpr (kCentreFromLds) {
+        uk = centre_cons(v);
+      } else {
+        uk = double(qk[e]);
+      }
+      const double qs = uk + dt * double(r);
       double out;
       if (st.stage == 1)
         out = qs;
