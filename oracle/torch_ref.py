@@ -1,4 +1,7 @@
-"""Plain PyTorch CPU float64 version of the five-equation RHS -- TEST ONLY.
+"""Plain PyTorch float64 version of the five-equation RHS -- TEST ONLY.
+
+It runs on the CPU; the adjoint test at the configuration's full size runs it
+on a GPU with torch's own kernels (nothing here depends on the device).
 
 The same discretization as ``oracle.c`` (same readings, same expression
 order) written with whole-array torch operations so that autograd yields
@@ -147,11 +150,11 @@ def pad_axis(P: Problem, q, d):
     else:
         m[high] = 2 * n - 1 - idx[high]
         flip[high] = True
-    qp = torch.index_select(q, ax, m)
+    qp = torch.index_select(q, ax, m.to(q.device))
     if flip.any():
         shape = [1, 1, 1, 1]
         shape[ax] = n + 6
-        sign = torch.where(flip, -1.0, 1.0).to(q.dtype).reshape(shape)
+        sign = torch.where(flip, -1.0, 1.0).to(dtype=q.dtype, device=q.device).reshape(shape)
         r = P.row_mom(d)
         qp = torch.cat([qp[:r], qp[r:r + 1] * sign, qp[r + 1:]], dim=0)
     return qp
