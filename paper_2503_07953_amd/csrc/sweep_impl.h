@@ -243,19 +243,28 @@ __global__ __launch_bounds__((Tile<DIR, D, Real>::NT)) void sweep_kernel(Params 
 
   // The accumulator of this thread's output cell is loaded here, so that its
   // latency hides behind the reconstruction: in the y pass, and in the float
-  // x pass (in the double x pass the 16 extra VGPRs cost a wave per SIMD and
-  // the pass got 12 % slower)
+  // x pass, which also loads q^n here (in the double x pass the 16 extra
+  // VGPRs cost a wave per SIMD and the pass got 12 % slower; it issues those
+  // loads together at the start of the update instead)
   constexpr bool kPrefetch =
       (DIR == 1 && MODE == MODE_ACC) || (DIR == 0 && D > 1 && (MODE & MODE_ACC) && sizeof(Real) == 4);
   // the y and z passes stream the accumulator with the non-temporal hint (the
   // y pass gained 4 % in FP64; in the x pass it cost 1.5-3 %)
   constexpr bool kNT = DIR != 0;
   Real pre[kPrefetch ? NEQ : 1];
+  constexpr bool kPrefetchQn = kPrefetch && DIR == 0 && (MODE & MODE_STEP) != 0;
+  Real preq[kPrefetchQn ? NEQ : 1];
   if constexpr (kPrefetch) {
     if (line_ok && a >= 1 && a <= TL::TA - 2 && c >= 0 && c < nd) {
       const long long cell = (DIR == 1) ? ((long long)oz * ny + c) * nx + ox : ((long long)oz * ny + oy) * nx + c;
 #pragma unroll
       for (int v = 0; v < NEQ; ++v) pre[v] = ld_acc<kNT>(&acc[v * nc + cell]);
+      if constexpr (kPrefetchQn) {
+        if (st.stage != 1) {
+#pragma unroll
+          for (int v = 0; v < NEQ; ++v) preq[v] = qn[v * nc + cell];
+        }
+      }
     }
   }
 
@@ -370,6 +379,24 @@ __global__ __launch_bounds__((Tile<DIR, D, Real>::NT)) void sweep_kernel(Params 
     if (v >= R::MOM && v < R::MOM + D) return ((NF == 2) ? w(0) + w(1) : w(0)) * w(v);
     return w(v);
   };
+  // the double x pass issues the accumulator and q^n loads of its output cell
+  // together, before any of them is used
+  constexpr bool kLoadsFirst = kLaneX && sizeof(Real) == 8 && (MODE & MODE_ACC) != 0;
+  constexpr bool kQnFirst = kLoadsFirst && (MODE & MODE_STEP) != 0;
+  Real accv[kLoadsFirst ? NEQ : 1];
+  Real qnl[kQnFirst ? NEQ : 1];
+  if constexpr (kLoadsFirst) {
+    if (out_ok) {
+#pragma unroll
+      for (int v = 0; v < NEQ; ++v) accv[v] = acc[v * nc + cell];
+      if constexpr (kQnFirst) {
+        if (st.stage != 1) {
+#pragma unroll
+          for (int v = 0; v < NEQ; ++v) qnl[v] = qn[v * nc + cell];
+        }
+      }
+    }
+  }
 #pragma unroll
   for (int v = 0; v < NEQ; ++v) {
     Real fhi;
@@ -388,6 +415,8 @@ __global__ __launch_bounds__((Tile<DIR, D, Real>::NT)) void sweep_kernel(Params 
     Real r = Dv;
     if constexpr (kPrefetch)
       r = pre[v] + Dv;
+    else if constexpr (kLoadsFirst)
+      r = accv[v] + Dv;
     else if constexpr (MODE & MODE_ACC)
       r = ld_acc<kNT>(&acc[e]) + Dv;
     if constexpr (MODE & MODE_STEP) {
@@ -401,12 +430,21 @@ __global__ __launch_bounds__((Tile<DIR, D, Real>::NT)) void sweep_kernel(Params 
       }
       const double qs = uk + dt * double(r);
       double out;
+      double qnv = 0.0;
+      if (st.stage != 1) {
+        if constexpr (kPrefetchQn)
+          qnv = double(preq[v]);
+        else if constexpr (kQnFirst)
+          qnv = double(qnl[v]);
+        else
+          qnv = double(qn[e]);
+      }
       if (st.stage == 1)
         out = qs;
       else if (st.stage == 2)
-        out = 0.75 * double(qn[e]) + 0.25 * qs;
+        out = 0.75 * qnv + 0.25 * qs;
       else
-        out = (1.0 / 3.0) * double(qn[e]) + (2.0 / 3.0) * qs;
+        out = (1.0 / 3.0) * qnv + (2.0 / 3.0) * qs;
       qout[e] = Real(out);
     } else {
       st_acc<kNT>(r, &acc[e]);
