@@ -168,7 +168,20 @@ __global__ __launch_bounds__((Tile<DIR, D, Real>::NT)) void sweep_kernel(Params 
   __shared__ double sred[kSignal ? TL::NT / 64 : 1];
   double smax = 0.0;
   bool sbad = false;
-  for (int L = tid; L < TL::SA * TL::TB; L += TL::NT) {
+  // A thread holds at most kIt cells of the tile (kIt = 2 for every tile
+  // shape).  In the x and z passes the loads of all of them are issued before
+  // the first conversion, so that a thread with two cells waits for memory
+  // once (x pass -1.2 %, z -0.8 %); the y pass, which prefetches its
+  // accumulator behind this phase, measured 2.5 % slower that way and
+  // converts each cell as it arrives.
+  constexpr int kCells = TL::SA * TL::TB;
+  constexpr int kIt = (kCells + TL::NT - 1) / TL::NT;
+  constexpr bool kBatchLoads = DIR != 1;
+  double U[kIt][NEQ];
+  int slot[kIt], line[kIt], cpos[kIt], cix[kIt][3];
+  bool live[kIt], flip[kIt];
+  auto load_cell = [&](int it) {
+    const int L = tid + it * TL::NT;
     int s, bb;
     if constexpr (DIR == 0) {
       bb = L / TL::SA;
@@ -187,31 +200,53 @@ __global__ __launch_bounds__((Tile<DIR, D, Real>::NT)) void sweep_kernel(Params 
       ix += bb;
       inb = ix < nx;
     }
-    if (!inb || pos > nd + 2) continue;
-    bool flip;
-    const int g = ghost_index(pos, nd, pm.bc_lo[DIR], pm.bc_hi[DIR], flip);
+    live[it] = L < kCells && inb && pos <= nd + 2;
+    slot[it] = s;
+    line[it] = bb;
+    cpos[it] = pos;
+    flip[it] = false;
+    if (!live[it]) return;
+    const int g = ghost_index(pos, nd, pm.bc_lo[DIR], pm.bc_hi[DIR], flip[it]);
     if constexpr (DIR == 0) ix = g;
     else if constexpr (DIR == 1) iy = g;
     else iz = g;
+    cix[it][0] = ix;
+    cix[it][1] = iy;
+    cix[it][2] = iz;
     const long long cell = ((long long)iz * ny + iy) * nx + ix;
-    double U[NEQ], W[NEQ];
 #pragma unroll
-    for (int v = 0; v < NEQ; ++v) U[v] = double(qk[v * nc + cell]);
-    if (flip) U[R::MOM + DIR] = -U[R::MOM + DIR];
-    cons_to_prim<NF, D>(pm, U, W);
+    for (int v = 0; v < NEQ; ++v) U[it][v] = double(qk[v * nc + cell]);
+  };
+  auto convert_cell = [&](int it) {
+    if (!live[it]) return;
+    const int s = slot[it], bb = line[it];
+    double W[NEQ];
+    if (flip[it]) U[it][R::MOM + DIR] = -U[it][R::MOM + DIR];
+    cons_to_prim<NF, D>(pm, U[it], W);
 #pragma unroll
     for (int v = 0; v < NEQ; ++v) sh[lds_index<DIR, D, Real>(v, s, bb)] = Real(W[v]);
     if constexpr (kSignal) {
-      if (s >= 3 && s < 3 + TL::OUT && pos < nd) {
+      if (s >= 3 && s < 3 + TL::OUT && cpos[it] < nd) {
         double ih[D];
-        const int cidx[3] = {ix, iy, iz};
 #pragma unroll
-        for (int d = 0; d < D; ++d) ih[d] = (WV == kWvNonUniform) ? inv_width(pm, d, cidx[d]) : pm.inv_dx[d];
+        for (int d = 0; d < D; ++d) ih[d] = (WV == kWvNonUniform) ? inv_width(pm, d, cix[it][d]) : pm.inv_dx[d];
         bool b;
-        const double sg = cell_signal<NF, D>(pm, U, W, b, ih);
+        const double sg = cell_signal<NF, D>(pm, U[it], W, b, ih);
         sbad |= b;
         smax = (sg > smax) ? sg : smax;  // NaN never wins; it is flagged instead
       }
+    }
+  };
+  if constexpr (kBatchLoads) {
+#pragma unroll
+    for (int it = 0; it < kIt; ++it) load_cell(it);
+#pragma unroll
+    for (int it = 0; it < kIt; ++it) convert_cell(it);
+  } else {
+#pragma unroll
+    for (int it = 0; it < kIt; ++it) {
+      load_cell(it);
+      convert_cell(it);
     }
   }
   if constexpr (kSignal) {
