@@ -396,7 +396,9 @@ __global__ __launch_bounds__((Tile<DIR, D, Real>::NT)) void sweep_kernel(Params 
   else if constexpr (DIR == 1) oy = c;
   else oz = c;
   const long long cell = ((long long)oz * ny + oy) * nx + ox;
-  const Real inv_dx = Real((WV == kWvNonUniform) ? inv_width(pm, DIR, c) : pm.inv_dx[DIR]);
+  // (x pass: every lane gets here, but only an output lane, 0 <= c < nd, may
+  // read the width table)
+  const Real inv_dx = Real((WV == kWvNonUniform) ? (out_ok ? inv_width(pm, DIR, c) : 0.0) : pm.inv_dx[DIR]);
   if constexpr (!kLaneX) uhi = sh[lds_index<DIR, D, Real>(NEQ, a + 1, b)];
   const Real div = inv_dx * (uhi - uf);
   // the centre's conservative values from its primitives (slot a + 2), each
