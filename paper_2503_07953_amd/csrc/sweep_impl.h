@@ -420,8 +420,18 @@ __global__ __launch_bounds__((Tile<DIR, D, Real>::NT)) void sweep_kernel(Params 
   // together, before any of them is used
   constexpr bool kLoadsFirst = kLaneX && sizeof(Real) == 8 && (MODE & MODE_ACC) != 0;
   constexpr bool kQnFirst = kLoadsFirst && (MODE & MODE_STEP) != 0;
+  // the float x pass takes q_k of its output cell from memory: those loads
+  // are issued together too
+  constexpr bool kQkFirst = kLaneX && sizeof(Real) == 4 && (MODE & MODE_STEP) != 0;
   Real accv[kLoadsFirst ? NEQ : 1];
   Real qnl[kQnFirst ? NEQ : 1];
+  Real qkl[kQkFirst ? NEQ : 1];
+  if constexpr (kQkFirst) {
+    if (out_ok) {
+#pragma unroll
+      for (int v = 0; v < NEQ; ++v) qkl[v] = qk[v * nc + cell];
+    }
+  }
   if constexpr (kLoadsFirst) {
     if (out_ok) {
 #pragma unroll
@@ -462,6 +472,8 @@ __global__ __launch_bounds__((Tile<DIR, D, Real>::NT)) void sweep_kernel(Params 
       double uk;
       if constexpr (kCentreFromLds) {
         uk = centre_cons(v);
+      } else if constexpr (kQkFirst) {
+        uk = double(qkl[v]);
       } else {
         uk = double(qk[e]);
       }
