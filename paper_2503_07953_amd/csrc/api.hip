@@ -616,12 +616,16 @@ hipError_t step_reverse(mfc_ctx* c, const double* qn, const double* q1, const do
                         const double* qnp1_bar, double* qn_bar, hipStream_t s) {
   const int nf = c->prob.num_fluids, nd = c->prob.ndim;
   const long long n = (long long)c->neq * c->ncell;
-  hipError_t e = mfc::launch_rhs_vjp(nf, nd, c->pm, q2, qnp1_bar, c->vbuf, c->vjp, false, s, c->timer);
-  if (e == hipSuccess) e = mfc::launch_adj_stage(3, n, dt, qnp1_bar, c->vbuf, c->b2, qn_bar, s);
-  if (e == hipSuccess) e = mfc::launch_rhs_vjp(nf, nd, c->pm, q1, c->b2, c->vbuf, c->vjp, false, s, c->timer);
-  if (e == hipSuccess) e = mfc::launch_adj_stage(2, n, dt, c->b2, c->vbuf, c->b1, qn_bar, s);
-  if (e == hipSuccess) e = mfc::launch_rhs_vjp(nf, nd, c->pm, qn, c->b1, c->vbuf, c->vjp, false, s, c->timer);
-  if (e == hipSuccess) e = mfc::launch_adj_stage(1, n, dt, c->b1, c->vbuf, nullptr, qn_bar, s);
+  // with every axis gathered in one cell pass the stage combination is applied
+  // there (no separate pass over v = vbuf); otherwise by launch_adj_stage
+  const bool fused = c->vjp.all_axes;
+  const mfc::StageEpi e3{3, dt, qnp1_bar, c->b2, qn_bar}, e2{2, dt, c->b2, c->b1, qn_bar}, e1{1, dt, c->b1, nullptr, qn_bar};
+  hipError_t e = mfc::launch_rhs_vjp(nf, nd, c->pm, q2, qnp1_bar, c->vbuf, c->vjp, false, s, c->timer, &e3);
+  if (e == hipSuccess && !fused) e = mfc::launch_adj_stage(3, n, dt, qnp1_bar, c->vbuf, c->b2, qn_bar, s);
+  if (e == hipSuccess) e = mfc::launch_rhs_vjp(nf, nd, c->pm, q1, c->b2, c->vbuf, c->vjp, false, s, c->timer, &e2);
+  if (e == hipSuccess && !fused) e = mfc::launch_adj_stage(2, n, dt, c->b2, c->vbuf, c->b1, qn_bar, s);
+  if (e == hipSuccess) e = mfc::launch_rhs_vjp(nf, nd, c->pm, qn, c->b1, c->vbuf, c->vjp, false, s, c->timer, &e1);
+  if (e == hipSuccess && !fused) e = mfc::launch_adj_stage(1, n, dt, c->b1, c->vbuf, nullptr, qn_bar, s);
   return e;
 }
 }  // namespace

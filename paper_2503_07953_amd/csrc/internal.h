@@ -95,8 +95,25 @@ struct VjpScratch {
   bool all_axes;
 };
 
+// Reverse SSP-RK3 stage combination applied to v = L^T rbar as the cell pass
+// writes it (stage 0: none, qbar = v or qbar += v):
+//   stage 3: out = 2/3 (x + dt v), qnb = x / 3
+//   stage 2: out = 1/4 (x + dt v), qnb += 3/4 x
+//   stage 1: qnb += x + dt v
+struct StageEpi {
+  int stage;
+  double dt;
+  const double* x;
+  double* out;
+  double* qnb;
+};
+// epi (stage > 0, accumulate false) is applied in the cell pass when every
+// axis is gathered in one pass (sc.all_axes), in place of writing qbar; with
+// the axes one after the other (!sc.all_axes) it is ignored, qbar is written,
+// and the caller applies the combination (launch_adj_stage).
 hipError_t launch_rhs_vjp(int nf, int ndim, const Params& pm, const double* q, const double* rbar, double* qbar,
-                          const VjpScratch& sc, bool accumulate, hipStream_t s, PassTimer* tm);
+                          const VjpScratch& sc, bool accumulate, hipStream_t s, PassTimer* tm,
+                          const StageEpi* epi = nullptr);
 hipError_t launch_convert_vjp(int nf, int ndim, bool to_cons, const Params& pm, const double* x, const double* ybar,
                               double* xbar, bool accumulate, hipStream_t s);
 hipError_t launch_adj_stage(int which, long long n, double dt, const double* x, const double* v, double* out,

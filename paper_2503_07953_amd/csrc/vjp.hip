@@ -12,14 +12,16 @@ MFC_EXTERN_VJP(3)
 MFC_EXTERN_VJP(4)
 
 hipError_t launch_rhs_vjp(int nf, int ndim, const Params& pm, const double* q, const double* rbar, double* qbar,
-                          const VjpScratch& sc, bool accumulate, hipStream_t s, PassTimer* tm) {
+                          const VjpScratch& sc, bool accumulate, hipStream_t s, PassTimer* tm, const StageEpi* epi) {
+  StageEpi none{0, 0.0, nullptr, nullptr, nullptr};
+  const StageEpi& ep = (epi && sc.all_axes) ? *epi : none;
   if (pm.nu[0] || pm.nu[1] || pm.nu[2])
-    return launch_rhs_vjp_wv<kWvNonUniform>(nf, ndim, pm, q, rbar, qbar, sc, accumulate, s, tm);
+    return launch_rhs_vjp_wv<kWvNonUniform>(nf, ndim, pm, q, rbar, qbar, sc, accumulate, s, tm, ep);
   switch (pm.weno_variant) {
-    case 1: return launch_rhs_vjp_wv<1>(nf, ndim, pm, q, rbar, qbar, sc, accumulate, s, tm);
-    case 2: return launch_rhs_vjp_wv<2>(nf, ndim, pm, q, rbar, qbar, sc, accumulate, s, tm);
-    case 3: return launch_rhs_vjp_wv<3>(nf, ndim, pm, q, rbar, qbar, sc, accumulate, s, tm);
-    default: return launch_rhs_vjp_wv<0>(nf, ndim, pm, q, rbar, qbar, sc, accumulate, s, tm);
+    case 1: return launch_rhs_vjp_wv<1>(nf, ndim, pm, q, rbar, qbar, sc, accumulate, s, tm, ep);
+    case 2: return launch_rhs_vjp_wv<2>(nf, ndim, pm, q, rbar, qbar, sc, accumulate, s, tm, ep);
+    case 3: return launch_rhs_vjp_wv<3>(nf, ndim, pm, q, rbar, qbar, sc, accumulate, s, tm, ep);
+    default: return launch_rhs_vjp_wv<0>(nf, ndim, pm, q, rbar, qbar, sc, accumulate, s, tm, ep);
   }
 }
 

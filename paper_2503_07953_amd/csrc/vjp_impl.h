@@ -398,7 +398,7 @@ __device__ __forceinline__ void gather_axis(const Params& pm, const double* __re
 template <int NF, int D, int D0, int D1>
 __global__ __launch_bounds__(256) void vjp_gather_kernel(Params pm, const double* __restrict__ q,
                                                          const double* __restrict__ rbar, VjpScratch sc,
-                                                         double* __restrict__ qbar, int accumulate) {
+                                                         double* __restrict__ qbar, int accumulate, StageEpi epi) {
   using R = Rows<NF, D>;
   constexpr int NEQ = R::NEQ;
   const long long nc = pm.ncell;
@@ -439,10 +439,24 @@ __global__ __launch_bounds__(256) void vjp_gather_kernel(Params pm, const double
 #pragma unroll
     for (int a = 0; a < 2; ++a) Ub[R::ALPHA + a] += rbar[(R::ALPHA + a) * nc + cell] * div;
   }
+  // qbar, or (epi.stage > 0) the reverse stage combination of v = Ub, the
+  // same operations as launch_adj_stage's
 #pragma unroll
   for (int v = 0; v < NEQ; ++v) {
     const long long e = v * nc + cell;
-    qbar[e] = accumulate ? qbar[e] + Ub[v] : Ub[v];
+    if (epi.stage == 3) {
+      const double x = epi.x[e];
+      epi.out[e] = (2.0 / 3.0) * (x + epi.dt * Ub[v]);
+      epi.qnb[e] = (1.0 / 3.0) * x;
+    } else if (epi.stage == 2) {
+      const double x = epi.x[e];
+      epi.out[e] = 0.25 * (x + epi.dt * Ub[v]);
+      epi.qnb[e] = epi.qnb[e] + 0.75 * x;
+    } else if (epi.stage == 1) {
+      epi.qnb[e] = epi.qnb[e] + (epi.x[e] + epi.dt * Ub[v]);
+    } else {
+      qbar[e] = accumulate ? qbar[e] + Ub[v] : Ub[v];
+    }
   }
 }
 
@@ -467,13 +481,14 @@ static hipError_t launch_axis_vjp(const Params& pm, const double* q, const doubl
   one.Gd[DIR] = sc.Gd[0];
   one.UFd[DIR] = sc.UFd[0];
   hipLaunchKernelGGL((vjp_gather_kernel<NF, D, DIR, DIR + 1>), dim3((unsigned)((pm.ncell + 255) / 256)), dim3(256), 0,
-                     s, pm, q, rbar, one, qbar, accumulate ? 1 : 0);
+                     s, pm, q, rbar, one, qbar, accumulate ? 1 : 0, StageEpi{0, 0.0, nullptr, nullptr, nullptr});
   return hipGetLastError();
 }
 
 template <int NF, int D, int WV, int RS>
 static hipError_t launch_rhs_vjp_t(const Params& pm, const double* q, const double* rbar, double* qbar,
-                                   const VjpScratch& sc, bool accumulate, hipStream_t s, PassTimer* tm) {
+                                   const VjpScratch& sc, bool accumulate, hipStream_t s, PassTimer* tm,
+                                   const StageEpi& epi) {
   hipError_t e = hipSuccess;
   if (tm) tm->begin(KIND_VJP, s);
   if (sc.all_axes) {
@@ -486,7 +501,7 @@ static hipError_t launch_rhs_vjp_t(const Params& pm, const double* q, const doub
     e = hipGetLastError();
     if (e == hipSuccess) {
       hipLaunchKernelGGL((vjp_gather_kernel<NF, D, 0, D>), dim3((unsigned)((pm.ncell + 255) / 256)), dim3(256), 0, s,
-                         pm, q, rbar, sc, qbar, accumulate ? 1 : 0);
+                         pm, q, rbar, sc, qbar, accumulate ? 1 : 0, epi);
       e = hipGetLastError();
     }
   } else {
@@ -501,9 +516,10 @@ static hipError_t launch_rhs_vjp_t(const Params& pm, const double* q, const doub
 // The face options are compile-time choices, as in the forward passes.
 template <int NF, int D, int WV>
 static hipError_t vjp_by_riemann(const Params& pm, const double* q, const double* rbar, double* qbar,
-                                 const VjpScratch& sc, bool accumulate, hipStream_t s, PassTimer* tm) {
+                                 const VjpScratch& sc, bool accumulate, hipStream_t s, PassTimer* tm,
+                                 const StageEpi& epi) {
 #define MFC_RS(B) \
-  case B: return launch_rhs_vjp_t<NF, D, WV, B>(pm, q, rbar, qbar, sc, accumulate, s, tm);
+  case B: return launch_rhs_vjp_t<NF, D, WV, B>(pm, q, rbar, qbar, sc, accumulate, s, tm, epi);
   switch (option_bits(pm)) {
     MFC_RS(0)
     MFC_RS(RS_HLL)
@@ -529,9 +545,10 @@ static hipError_t vjp_by_riemann(const Params& pm, const double* q, const double
 // Every grid of one reconstruction variant.
 template <int WV>
 hipError_t launch_rhs_vjp_wv(int nf, int ndim, const Params& pm, const double* q, const double* rbar, double* qbar,
-                             const VjpScratch& sc, bool accumulate, hipStream_t s, PassTimer* tm) {
+                             const VjpScratch& sc, bool accumulate, hipStream_t s, PassTimer* tm,
+                             const StageEpi& epi) {
 #define MFC_CASE(NF, D) \
-  if (nf == NF && ndim == D) return vjp_by_riemann<NF, D, WV>(pm, q, rbar, qbar, sc, accumulate, s, tm);
+  if (nf == NF && ndim == D) return vjp_by_riemann<NF, D, WV>(pm, q, rbar, qbar, sc, accumulate, s, tm, epi);
   MFC_CASE(1, 1)
   MFC_CASE(1, 2)
   MFC_CASE(1, 3)
@@ -544,7 +561,7 @@ hipError_t launch_rhs_vjp_wv(int nf, int ndim, const Params& pm, const double* q
 
 #define MFC_VJP_DECL(KW, WV)                                                                                 \
   KW template hipError_t launch_rhs_vjp_wv<WV>(int, int, const Params&, const double*, const double*, double*, \
-                                               const VjpScratch&, bool, hipStream_t, PassTimer*);
+                                               const VjpScratch&, bool, hipStream_t, PassTimer*, const StageEpi&);
 #define MFC_INSTANTIATE_VJP(WV) MFC_VJP_DECL(, WV)
 #define MFC_EXTERN_VJP(WV) MFC_VJP_DECL(extern, WV)
 
