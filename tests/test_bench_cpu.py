@@ -45,3 +45,18 @@ def test_roofline_fields_and_traffic_guard():
     assert r["frac"] == pytest.approx(r["achieved"] / r["peak"], rel=1e-3)
     # a different grid size never picks up the committed 256^3 counters
     assert bench.measured_traffic_bytes("pass_x", "fp64", 100) is None
+
+
+def test_committed_counter_summaries_match_the_committed_kernels():
+    """The traffic and VALU summaries under profiles/ were taken on the kernel
+    sources as committed (sha256 of the files each lists), at the bubble cloud's
+    256^3 cells, so the bench line's `traffic` and counter-based fractions are
+    not null and not stale; every pass of both precisions has its bytes."""
+    n = 256 ** 3
+    traffic = bench._profile_data(bench.TRAFFIC_FILE, "traffic-data:", n)
+    assert traffic is not None, "profiles/hbm_traffic_bubble_cloud_256.md is stale: re-profile the sweeps"
+    for kind in ("pass_x", "pass_y", "pass_z"):
+        for prec in ("fp64", "fp32"):
+            assert bench.measured_traffic_bytes(kind, prec, n) > 0
+    for kind in ("pass_x", "pass_y", "pass_z"):
+        assert bench.measured_valu(kind, n) > 0, "profiles/valu_sweep_bubble_cloud_256_fp64.md is stale"
